@@ -1,0 +1,87 @@
+"""Closed-form solvation energies of a dielectric sphere (pins of the oracle).
+
+TEST INFRASTRUCTURE ONLY.
+
+All energies in kcal/mol with K = 332.06 kcal A/(mol e^2), charges in e,
+lengths in A.  A sphere of radius ``a`` (permittivity eps_in) in a medium of
+permittivity eps_out, point charges q_i at r_i with |r_i| < a.
+
+* Born ion (one charge at the centre):
+      dG = -(K q^2 / 2a) (1/eps_in - 1/eps_out).
+* Kirkwood reaction-field series (textbook solution of the Section 2.1
+  model for a sphere):
+      dG = (K/2) sum_ij q_i q_j sum_n c_n (|r_i||r_j|)^n / a^(2n+1) P_n(cos g_ij),
+      c_n = (n+1)(eps_in - eps_out) / (eps_in (n eps_in + (n+1) eps_out)).
+* BIBEE sphere series (eq. CFA and the scale-factor-0 variant of Section 2.2,
+  applied to the sphere analytically): the surface charge is f times the
+  normal field (CFA) or f/(1 - f/2) times it (P), which gives the same
+  series with
+      c_n^CFA = -f (n+1) / (eps_in (2n+1)),
+      c_n^P   = -(f / (1 - f/2)) (n+1) / (eps_in (2n+1)).
+  For n = 0, c_0 = c_0^CFA: the CFA is exact for a centred charge, whose
+  normal field is uniform on the sphere.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+K_COULOMB = 332.06
+
+
+def born(q: float, R: float, eps_in: float, eps_out: float) -> float:
+    return -(K_COULOMB * q * q / (2.0 * R)) * (1.0 / eps_in - 1.0 / eps_out)
+
+
+def _legendre_all(nmax: int, x: np.ndarray) -> np.ndarray:
+    """P_0..P_nmax at x (Bonnet recurrence)."""
+    P = np.zeros((nmax + 1,) + x.shape)
+    P[0] = 1.0
+    if nmax >= 1:
+        P[1] = x
+    for n in range(2, nmax + 1):
+        P[n] = ((2 * n - 1) * x * P[n - 1] - (n - 1) * P[n - 2]) / n
+    return P
+
+
+def _coeffs(kind: str, nmax: int, eps_in: float, eps_out: float) -> np.ndarray:
+    n = np.arange(nmax + 1, dtype=np.float64)
+    f = 1.0 - eps_in / eps_out
+    if kind == "exact":
+        return (n + 1) * (eps_in - eps_out) / (eps_in * (n * eps_in + (n + 1) * eps_out))
+    if kind == "cfa":
+        return -f * (n + 1) / (eps_in * (2 * n + 1))
+    if kind == "p":
+        return -(f / (1.0 - 0.5 * f)) * (n + 1) / (eps_in * (2 * n + 1))
+    raise ValueError(kind)
+
+
+def _series_matrix(pos, a, nmax, c):
+    pos = np.asarray(pos, dtype=np.float64)
+    r = np.linalg.norm(pos, axis=1)
+    rr = np.outer(r, r)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        cosg = (pos @ pos.T) / rr
+    cosg = np.where(rr > 0, cosg, 1.0)
+    cosg = np.clip(cosg, -1.0, 1.0)
+    P = _legendre_all(nmax, cosg)
+    t = rr / (a * a)
+    M = np.zeros_like(rr)
+    tn = np.ones_like(rr)
+    for n in range(nmax + 1):
+        M += c[n] * tn * P[n]
+        tn = tn * t
+    return M / a  # (K/2) q^T M q is the energy
+
+
+def sphere_energy(pos, q, a, eps_in, eps_out, kind="exact", nmax=60) -> float:
+    """Solvation energy of charges inside a sphere: kind in {exact, cfa, p}."""
+    q = np.asarray(q, dtype=np.float64)
+    M = _series_matrix(pos, a, nmax, _coeffs(kind, nmax, eps_in, eps_out))
+    return 0.5 * K_COULOMB * float(q @ M @ q)
+
+
+def sphere_energy_grad_q(pos, q, a, eps_in, eps_out, kind="exact", nmax=60) -> np.ndarray:
+    """d dG / d q_i = K sum_j M_ij q_j (M symmetric)."""
+    q = np.asarray(q, dtype=np.float64)
+    M = _series_matrix(pos, a, nmax, _coeffs(kind, nmax, eps_in, eps_out))
+    return K_COULOMB * (M @ q)
