@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark of the FMM-BEM hot path on one MI355X.
+
+One step = one pass of the whole hot path over one synthetic molecule,
+inputs already resident in HBM: build the octree (geometry, Morton sort,
+cells, lists) -> solve A x = f B q to a 1e-6 relative residual with
+FP32-FMM GMRES inside FP64 iterative refinement -> solvation energy ->
+BIBEE/CFA energy -> adjoint gradient (d dG/dq and d dG/dr).  `value` is
+panels per second through that whole step.
+
+Also reported (outside the timed steps): FP32 and FP64 matvec panels/s,
+time to a 1e-6 residual for the plain FP64 and the FP32-refined solves,
+sampled-row error of the matvec against the FP64 dense oracle, the
+roofline of the dominant kernel from HIP events on the library's stream,
+and the oracle's own speed on the host cores (a reported baseline).
+
+Usage: python bench.py [--steps K] [--warmup W] [--config blobby|crowded|kirkwood]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+METRIC = "BEM-FMM matvec panels/s + solve time to 1e-6 rel residual, FP32 vs FP64"
+PEAK_FP32_VALU = 157.3e12    # MI355X FP32 vector (packed) FLOP/s
+PEAK_FP32_MFMA = 157.3e12    # MI355X dense FP32 MFMA FLOP/s
+P2P_FLOPS_PER_PAIR = 18      # K' monopole pair: 3 sub, 5 for r^2, 1 rsq, 3 mul, 6 for 3 FMA
+M2L_FLOPS_PER_PAIR = 2 * 100 * 100   # dense p^2 x p^2 contraction at p = 10
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="blobby")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=4096)
+    ap.add_argument("--matvec-reps", type=int, default=20)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU design is documented, not built); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_1007_4591_amd as B
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    prob = synth.config(args.config)
+    N, Q = prob.n_panels, prob.n_charges
+    print(f"[bench] config={args.config} N={N} Q={Q}", file=sys.stderr, flush=True)
+    verts = torch.as_tensor(prob.verts, device=dev)
+    tris = torch.as_tensor(prob.tris, device=dev)
+    cpos = torch.as_tensor(prob.charge_pos, device=dev)
+    q = torch.as_tensor(prob.q, device=dev)
+    params = B.Params(p=10, ncrit=64, theta=0.5, mac=B.MAC_THETA, eps_in=prob.eps_in, eps_out=prob.eps_out)
+    TOL = 1e-6
+
+    def step():
+        t = B.build_tree(verts, tris, cpos, params)
+        x, info = B.solve_bem(t, q, tol=TOL, maxit=300, restart=30, precision=B.FP32_REFINED)
+        dG = B.solvation_energy(t, q, x, precision=B.FP64)
+        bib = B.bibee_energy(t, q, kind=B.BIBEE_CFA, precision=B.FP32)
+        dq, dpos, ainfo = B.adjoint_grad(t, q, x, tol=TOL, maxit=300, restart=30, precision=B.FP32_REFINED)
+        return t, x, info, ainfo, dG, bib
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(args.steps):
+        last = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1000.0 * dt / args.steps
+    tree, x, sinfo, ainfo, dG, bib = last
+    print(f"[bench] step {ms_per_step:.2f} ms dG={dG:.6f} bibee={bib:.6f} solve iters={sinfo.iters} "
+          f"outer={sinfo.outer_iters} adjoint iters={ainfo.iters}", file=sys.stderr, flush=True)
+
+    # ---- matvec throughput and stage profile (HIP events on the stream)
+    rng = np.random.default_rng(1)
+    xv = torch.as_tensor(rng.normal(size=N), device=dev)
+    yv = torch.empty(N, dtype=torch.float64, device=dev)
+    mv = {}
+    for prec, name in ((B.FP32, "fp32"), (B.FP64, "fp64")):
+        for _ in range(3):
+            B.fmm_matvec(tree, B.OP_A, prec, xv, yv)
+        times = []
+        for _ in range(args.matvec_reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            B.fmm_matvec(tree, B.OP_A, prec, xv, yv)
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1) / 1000.0)
+        mv[name] = {"median_ms": 1000 * statistics.median(times), "panels_per_s": N / statistics.median(times)}
+    print(f"[bench] matvec {mv}", file=sys.stderr, flush=True)
+    # per-stage times of the FP32 matvec
+    B.profile(tree, True, True)
+    nprof = 5
+    for _ in range(nprof):
+        B.fmm_matvec(tree, B.OP_A, B.FP32, xv, yv)
+    stages = {s: B.profile_get(tree, s) for s in ("p2m", "m2m", "m2l", "l2l", "p2p", "other")}
+    B.profile(tree, False, True)
+    info = tree.info
+    p2p_ms = stages["p2p"][0] / max(stages["p2p"][1], 1)
+    m2l_ms = stages["m2l"][0] / max(stages["m2l"][1], 1)
+    p2p_flops = info["p2p_pairs_panels"] * P2P_FLOPS_PER_PAIR
+    m2l_flops = info["n_far_pairs"] * M2L_FLOPS_PER_PAIR
+    roof_p2p = {"bound": "alu", "kernel": "k_p2p (P2P + L2P, FP32)", "achieved": p2p_flops / (p2p_ms / 1e3) / 1e12,
+                "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s", "avg_ms": p2p_ms, "traffic": None}
+    roof_p2p["frac"] = roof_p2p["achieved"] / roof_p2p["peak"]
+    roof_m2l = {"bound": "mfma", "kernel": "k_m2l_f32 (M2L, FP32 MFMA)", "achieved": m2l_flops / (m2l_ms / 1e3) / 1e12,
+                "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "avg_ms": m2l_ms, "traffic": None}
+    roof_m2l["frac"] = roof_m2l["achieved"] / roof_m2l["peak"]
+    roofline = roof_p2p if p2p_ms >= m2l_ms else roof_m2l
+    print(f"[bench] stages(ms, count)={stages}", file=sys.stderr, flush=True)
+
+    # ---- solve time to 1e-6: plain FP64 vs FP32-refined
+    solves = {}
+    for prec, name in ((B.FP64, "fp64"), (B.FP32_REFINED, "fp32_refined")):
+        B.solve_bem(tree, q, tol=TOL, maxit=300, precision=prec)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        _, si = B.solve_bem(tree, q, tol=TOL, maxit=300, precision=prec)
+        torch.cuda.synchronize()
+        solves[name] = {"seconds": time.perf_counter() - s0, "iters": si.iters, "outer": si.outer_iters,
+                        "rel_residual": si.rel_residual}
+    print(f"[bench] solves {solves}", file=sys.stderr, flush=True)
+
+    # ---- error vs the FP64 dense oracle on sampled rows, and the oracle's speed
+    err = {}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        g = oracle.geometry(prob.verts, prob.tris)
+        rows = np.sort(np.random.default_rng(2).choice(N, size=min(args.cpu_rows, N), replace=False))
+        xh = xv.cpu().numpy()
+        c0 = time.perf_counter()
+        want = oracle.apply_A(g, 1.0 - prob.eps_in / prob.eps_out, xh, rows=rows)
+        cpu_s = time.perf_counter() - c0
+        for prec, name in ((B.FP32, "fp32"), (B.FP64, "fp64")):
+            got = B.fmm_matvec(tree, B.OP_A, prec, xv).cpu().numpy()[rows]
+            err[name] = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+        t_matvec_cpu = cpu_s / len(rows) * N
+        n_mv = sinfo.iters + sinfo.outer_iters + ainfo.iters + ainfo.outer_iters + 6
+        cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        omp = int(os.environ.get("OMP_NUM_THREADS", cores))
+        cpu = {"value": N / (t_matvec_cpu * n_mv), "unit": "panels/s", "cores": min(cores, omp), "kind": "oracle",
+               "sample": (f"{len(rows)} rows of the dense FP64 A x (oracle, OpenMP) at N={N}: {cpu_s:.2f} s; "
+                          f"projected dense matvec {t_matvec_cpu:.1f} s x {n_mv} matvec-equivalents per step"),
+               "matvec_panels_per_s": N / t_matvec_cpu}
+        print(f"[bench] sampled-row error vs oracle {err}; cpu {cpu}", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC, "value": N / (ms_per_step / 1e3), "unit": "panels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{prob.name}: {N} panels, {Q} charges, eps 4/80, p=10, theta=0.5, ncrit=64; "
+                               "step = tree build + FP32-refined solve to 1e-6 + energy + BIBEE + adjoint",
+                   "panels": N, "charges": Q},
+        "matvec": {k: {"panels_per_s": v["panels_per_s"], "ms": v["median_ms"], "rel_err_vs_oracle": err.get(k)}
+                   for k, v in mv.items()},
+        "solve_to_1e-6": solves,
+        "energies": {"dG_kcal_mol": dG, "bibee_cfa_kcal_mol": bib},
+        "stages_ms_per_matvec_fp32": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+        "tree": {k: info[k] for k in ("leaf_level", "n_cells", "n_leaves", "n_near_pairs", "n_far_pairs",
+                                      "n_offsets", "p2p_pairs_panels")},
+        "roofline": roofline,
+        "roofline_other": roof_m2l if roofline is roof_p2p else roof_p2p,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

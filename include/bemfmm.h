@@ -1,0 +1,227 @@
+/*
+ * bemfmm -- fast-multipole boundary-element electrostatics on one MI355X.
+ *
+ * The method is that of Yokota, Bardhan, Knepley, Barba and Hamada,
+ * "Biomolecular electrostatics using a fast multipole BEM on up to 512 GPUs
+ * and a billion unknowns" (arXiv:1007.4591):
+ *
+ *   Section 2.1 (continuum model, eq. ASC, eq. reac, matrix statement):
+ *     flat triangular panels, one piecewise-constant unknown per panel,
+ *     one quadrature point at the centroid;  A x = f E,  E = B q,
+ *     A = (1 - f/2) I - f K',  f = 1 - eps_in/eps_out,
+ *     K'_ij = a_j n_i . grad G(c_i, c_j), K'_ii = 0,  G = 1/(4 pi |r - r'|),
+ *     phi = C x,  (C x)_q = sum_j a_j x_j G(r_q, c_j),
+ *     dG = (2 pi K / eps_in) q^T C x,  K = 332.06 kcal A / (mol e^2).
+ *   Section 2.2 (BIBEE, eq. CFA): BIBEE/CFA takes x = f E, BIBEE/P takes
+ *     x = f E / (1 - f/2); the energy is then computed as above.
+ *   Section 2.3 (FMM): every product with K', B, C and their transposes is
+ *     a fast-multipole sum over an octree (P2M, M2M, M2L, L2L, L2P, P2P).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Arrays are DEVICE pointers (memory of the current HIP device), FP64, in
+ *   the caller's original order, row-major (x,y,z) for 3-vectors, unless the
+ *   argument name ends in _host.  The caller owns every argument buffer;
+ *   the library copies what it keeps, so inputs may be freed after a call.
+ * - All device work is enqueued on `stream` (a hipStream_t; NULL is the
+ *   null stream).  Entry points that return host scalars or solve iteratively
+ *   synchronise that stream.  A tree may be used by one stream at a time.
+ * - Every function returns a bemfmm_status.  On failure, outputs are
+ *   unspecified and bemfmm_last_error() returns a message (thread-local).
+ *   The tree stays valid except after BEMFMM_EDEVICE.
+ * - Expansion order p means degrees 0..p-1 (p^2 real coefficients per
+ *   expansion; p = 10 gives the 55 complex coefficients of Section 3.2).
+ */
+#ifndef BEMFMM_H
+#define BEMFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bemfmm_tree bemfmm_tree; /* opaque; owns its device memory */
+
+typedef enum {
+  BEMFMM_OK = 0,
+  BEMFMM_EINVAL = 1,  /* bad argument, mesh or parameter */
+  BEMFMM_ENOMEM = 2,  /* device allocation failed */
+  BEMFMM_EDEVICE = 3, /* HIP runtime error */
+  BEMFMM_ENOCONV = 4, /* iterative solve reached maxit; outputs hold the last iterate */
+  BEMFMM_ESTATE = 5   /* NULL or destroyed tree */
+} bemfmm_status;
+
+typedef enum {
+  BEMFMM_FP64 = 0,        /* every FMM stage in FP64 */
+  BEMFMM_FP32 = 1,        /* P2P and expansions in FP32 (M2L on FP32 MFMA) */
+  BEMFMM_FP32_REFINED = 2 /* solves: FP32 inner GMRES inside an FP64-residual
+                             iterative refinement; single products: as FP32 */
+} bemfmm_precision;
+
+typedef enum {
+  BEMFMM_OP_A = 0,  /* y[N] = (1 - f/2) x - f K' x,            x[N]   */
+  BEMFMM_OP_AT = 1, /* y[N] = (1 - f/2) x - f K'^T x,          x[N]   */
+  BEMFMM_OP_B = 2,  /* y[N] = E = B x (normal field),          x[Q]   */
+  BEMFMM_OP_BT = 3, /* y[Q] = B^T x = DL(x)(r_q),              x[N]   */
+  BEMFMM_OP_C = 4,  /* y[Q] = C x,                             x[N]   */
+  BEMFMM_OP_CT = 5  /* y[N] = C^T x,                           x[Q]   */
+} bemfmm_op;
+
+typedef enum { BEMFMM_BIBEE_CFA = 0, BEMFMM_BIBEE_P = 1 } bemfmm_bibee;
+
+/* Multipole acceptance between two same-level cells whose integer offset
+ * (in cell widths) is o:
+ *   THETA:    far iff 3 < theta^2 |o|^2, i.e. (R_a + R_b) < theta |d| with
+ *             R the box half-diagonal (strict; ties are near);
+ *   ADJACENT: far iff max|o_i| > 1 (the interaction list of Section 2.3:
+ *             children of the parent's neighbours that are not adjacent). */
+typedef enum { BEMFMM_MAC_THETA = 0, BEMFMM_MAC_ADJACENT = 1 } bemfmm_mac;
+
+typedef struct {
+  int p;          /* expansion order, 1..12 (degrees 0..p-1) */
+  int ncrit;      /* leaf level = shallowest level with mean panels per
+                     non-empty cell <= ncrit (uniform-depth sparse octree) */
+  double theta;   /* MAC parameter for BEMFMM_MAC_THETA, 0.2..1 */
+  int mac;        /* bemfmm_mac */
+  double eps_in;  /* solute permittivity > 0 */
+  double eps_out; /* solvent permittivity > 0 */
+} bemfmm_params;
+
+typedef struct {
+  int iters;           /* total inner (matvec) iterations */
+  int outer_iters;     /* refinement steps (1 for plain solves) */
+  int converged;       /* 1 if rel_residual <= tol */
+  double rel_residual; /* explicit |b - A x| / |b| with the FP64 FMM operator */
+  double seconds;      /* wall time of the call */
+} bemfmm_solve_info;
+
+typedef struct {
+  int64_t n_panels, n_charges;
+  int leaf_level;           /* L */
+  int64_t n_cells;          /* all levels 0..L */
+  int64_t n_leaves;
+  int64_t n_near_pairs;     /* leaf-level near (P2P) cell pairs */
+  int64_t n_far_pairs;      /* M2L cell pairs, all levels */
+  int64_t n_offsets;        /* distinct M2L translation offsets */
+  int64_t p2p_pairs_panels; /* sum over near cell pairs of n_t * n_s (panels -> panels) */
+  double lo[3];             /* root cube corner */
+  double side;              /* root cube side */
+} bemfmm_tree_info;
+
+/* Build the octree and interaction lists for a mesh and a set of charges
+ * (Section 2.3 hierarchy; Section 3.1 Morton ordering), entirely on the GPU:
+ * panel geometry, bounding cube, 30-bit Morton keys, stable radix sort,
+ * cells of every level, near (P2P) and far (M2L) lists grouped by
+ * translation offset.  verts: [nv*3]; tris: [nt*3] int32 vertex indices,
+ * counter-clockwise seen from outside (the normal points into the solvent);
+ * charge_pos: [nq*3] (nq may be 0).  The mesh is fixed for the tree's
+ * lifetime.  EINVAL: nt == 0, an index out of range, a zero-area or
+ * non-finite triangle, a non-finite charge, or parameters out of range.
+ * *out receives a new tree, to be released with bemfmm_tree_destroy. */
+int bemfmm_build_tree(const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                      const double *charge_pos, int64_t nq, const bemfmm_params *params,
+                      void *stream, bemfmm_tree **out);
+
+/* Move the charges (charge_pos [nq*3], same count and order) without
+ * rebuilding: every charge keeps its leaf cell, so the FMM operator changes
+ * continuously (finite differences on a frozen tree).  EINVAL if a charge
+ * leaves its leaf box by more than a quarter of the leaf side. */
+int bemfmm_set_charges(bemfmm_tree *tree, const double *charge_pos, void *stream);
+
+int bemfmm_tree_destroy(bemfmm_tree *tree);
+
+/* Sizes of the built tree (host struct). */
+int bemfmm_tree_get_info(const bemfmm_tree *tree, bemfmm_tree_info *info_host);
+
+/* One fast-multipole product with the operator `op` (see bemfmm_op):
+ * x and y are device FP64 arrays of the sizes listed there.  The result is
+ * the FMM approximation of the dense discrete operator of Section 2.1. */
+int bemfmm_fmm_matvec(bemfmm_tree *tree, int op, int precision, const double *x, double *y,
+                      void *stream);
+
+/* Solve A x = f B q (Section 2.1) by GMRES(restart) from x = 0 until the
+ * explicit relative residual |f B q - A x| / |f B q| (FP64 FMM operator)
+ * is <= tol or maxit inner iterations were spent.  q: [Q]; x: [N] output.
+ * precision FP32_REFINED runs FP32-FMM GMRES inside an FP64 refinement
+ * loop.  info_host may be NULL.  ENOCONV if not converged. */
+int bemfmm_solve_bem(bemfmm_tree *tree, const double *q, double *x, double tol, int maxit,
+                     int restart, int precision, bemfmm_solve_info *info_host, void *stream);
+
+/* BIBEE energy (Section 2.2, eq. CFA and its scale-factor-0 variant):
+ * x = f E (CFA) or f E / (1 - f/2) (P), then dG = (2 pi K/eps_in) q^T C x,
+ * written to *dG_host in kcal/mol.  q: [Q]. */
+int bemfmm_bibee_energy(bemfmm_tree *tree, const double *q, int kind, int precision,
+                        double *dG_host, void *stream);
+
+/* Solvation energy dG = (2 pi K/eps_in) q^T C x for a given surface charge
+ * x [N] (Section 2.1 energy; C by FMM), in kcal/mol, to *dG_host. */
+int bemfmm_solvation_energy(bemfmm_tree *tree, const double *q, const double *x, int precision,
+                            double *dG_host, void *stream);
+
+/* Gradient of dG(q, r) = kappa q^T C A^-1 f B q (kappa = 2 pi K/eps_in),
+ * given the forward solution x [N] of A x = f B q: solves A^T y = C^T q
+ * (the transposed operator is a dipole-source FMM) and returns
+ *   dG_dq   [Q]   = kappa (C x + f B^T y),
+ *   dG_dpos [Q*3] = kappa q_q [grad SL(a x) + f grad DL(y)](r_q)
+ * (the force on charge q is -dG_dpos; the mesh is held fixed).
+ * Either output may be NULL.  info_host (may be NULL) describes the
+ * adjoint solve. */
+int bemfmm_adjoint_grad(bemfmm_tree *tree, const double *q, const double *x, double tol, int maxit,
+                        int restart, int precision, double *dG_dq, double *dG_dpos,
+                        bemfmm_solve_info *info_host, void *stream);
+
+/* Thread-local message for the last failure on this thread ("" if none). */
+const char *bemfmm_last_error(void);
+
+/* ----------------------------------------------------------------------
+ * Inspection (used by parity tests; not needed to solve).
+ * ---------------------------------------------------------------------- */
+
+/* Copy tree arrays to host buffers the caller allocated with the sizes from
+ * bemfmm_tree_info.  Any pointer may be NULL.
+ *   panel_perm [N], charge_perm [Q]: sorted position -> caller index.
+ *   panel_key [N], charge_key [Q]: 30-bit Morton keys in sorted order.
+ *   cell_key [n_cells] (level prefix), cell_level [n_cells],
+ *   cell_range [n_cells*4] = panel begin, end, charge begin, end,
+ *   cell_parent [n_cells] (global cell index, -1 for the root);
+ *   cells are stored level by level (0..L), each level in increasing key.
+ *   near_ptr [n_leaves+1], near_idx [n_near_pairs]: leaf-level CSR, leaf
+ *   indices local to level L, sources in increasing order;
+ *   far_pairs [n_far_pairs*3] = (level, target, source) with level-local
+ *   indices, ordered by level, then target, then source. */
+int bemfmm_tree_export(const bemfmm_tree *tree, int32_t *panel_perm_host, int32_t *charge_perm_host,
+                       uint32_t *panel_key_host, uint32_t *charge_key_host,
+                       uint32_t *cell_key_host, int32_t *cell_level_host, int32_t *cell_range_host,
+                       int32_t *cell_parent_host, int32_t *near_ptr_host, int32_t *near_idx_host,
+                       int32_t *far_pairs_host);
+
+/* Expansions left by the last bemfmm_fmm_matvec at `precision` on this
+ * tree: which = 0 for multipole, 1 for local; out_host [n_cells * p*p]
+ * FP64, cell-major in the cell order of bemfmm_tree_export, scaled and
+ * packed as: a cell of side s stores M_n^m / s^n and s^(n+1) L_n^m of the
+ * 1/|x-y| kernel, with R_n^m = r^n P_n^m(cos t) e^{i m phi}/(n+m)! and
+ * I_n^m = (n-m)! P_n^m(cos t) e^{i m phi}/r^(n+1) (Condon-Shortley phase),
+ * M_n^m = sum w conj(R_n^m(y - X)), L_n^m = sum w conj(I_n^m(y - X));
+ * per degree n: Re m=0, then Re, Im of m = 1..n. */
+int bemfmm_debug_expansions(bemfmm_tree *tree, int precision, int which, double *out_host);
+
+/* Near (P2P) and far (L2P) parts of the raw field of the last
+ * bemfmm_fmm_matvec at `precision`, per target in the caller's order,
+ * before the operator's combination (kernel 1/(4 pi |x - y|)): for panel
+ * targets the normal derivative (A, B) or potential (A^T, C^T); for charge
+ * targets the potential.  near_host, far_host: [n_targets]. */
+int bemfmm_debug_fields(bemfmm_tree *tree, int precision, double *near_host, double *far_host);
+
+/* Per-stage device time of matvecs since the last reset, from HIP events on
+ * the stream (enable = 1 starts recording, 0 stops; reset clears).  stage
+ * names: "p2m", "m2m", "m2l", "l2l", "p2p" (includes L2P and the final
+ * combination), "other".  ms_host and count_host receive totals. */
+int bemfmm_profile(bemfmm_tree *tree, int enable, int reset);
+int bemfmm_profile_get(bemfmm_tree *tree, const char *stage, double *ms_host, int64_t *count_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEMFMM_H */

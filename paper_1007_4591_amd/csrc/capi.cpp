@@ -1,0 +1,254 @@
+// C-ABI of the library: argument checks, error mapping, tree lifetime.
+// No C++ exception crosses this boundary.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "common.h"
+
+namespace bemfmm {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+Tree::~Tree() {
+  fmm_free(*this);
+  if (ev_init)
+    for (auto &e : ev) (void)hipEventDestroy(e);
+  magic = 0;
+}
+
+Tree *check_tree(const bemfmm_tree *t) {
+  Tree *T = reinterpret_cast<Tree *>(const_cast<bemfmm_tree *>(t));
+  if (!T || T->magic != 0x5eedbe11) BF_THROW(BEMFMM_ESTATE, "NULL or destroyed tree");
+  return T;
+}
+
+template <class F>
+static int guard(F &&f) {
+  g_err.clear();
+  try {
+    f();
+    return BEMFMM_OK;
+  } catch (const Error &e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_err = "host allocation failed";
+    return BEMFMM_ENOMEM;
+  } catch (const std::exception &e) {
+    g_err = e.what();
+    return BEMFMM_EDEVICE;
+  }
+}
+
+static void need(bool ok, const char *msg) {
+  if (!ok) BF_THROW(BEMFMM_EINVAL, msg);
+}
+
+
+}  // namespace bemfmm
+
+using namespace bemfmm;
+
+extern "C" {
+
+int bemfmm_build_tree(const double *verts, int64_t nv, const int32_t *tris, int64_t nt, const double *charge_pos,
+                      int64_t nq, const bemfmm_params *params, void *stream, bemfmm_tree **out) {
+  return guard([&] {
+    need(out != nullptr, "out is NULL");
+    *out = nullptr;
+    need(params != nullptr, "params is NULL");
+    need(nt > 0 && nv > 0, "empty mesh");
+    need(nt < (int64_t)1 << 30 && nq < (int64_t)1 << 30, "too many panels or charges (int32 indices)");
+    need(verts && tris, "verts/tris are NULL");
+    need(nq == 0 || charge_pos, "charge_pos is NULL");
+    need(nq >= 0, "nq < 0");
+    const bemfmm_params &P = *params;
+    need(P.p >= 1 && P.p <= PMAX, "p outside 1..12");
+    need(P.ncrit >= 1, "ncrit < 1");
+    need(P.mac == BEMFMM_MAC_THETA || P.mac == BEMFMM_MAC_ADJACENT, "unknown MAC");
+    need(P.mac == BEMFMM_MAC_ADJACENT || (P.theta >= 0.3 && P.theta <= 1.0), "theta outside [0.3, 1]");
+    need(P.eps_in > 0 && P.eps_out > 0 && std::isfinite(P.eps_in) && std::isfinite(P.eps_out),
+         "permittivities must be positive");
+    Tree *T = new Tree();
+    try {
+      HIP_OK(hipGetDevice(&T->device));
+      T->prm = P;
+      build_tree(*T, verts, nv, tris, nt, charge_pos, nq, (hipStream_t)stream);
+    } catch (...) {
+      delete T;
+      throw;
+    }
+    *out = reinterpret_cast<bemfmm_tree *>(T);
+  });
+}
+
+int bemfmm_set_charges(bemfmm_tree *tree, const double *charge_pos, void *stream) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    need(T->Q == 0 || charge_pos, "charge_pos is NULL");
+    set_charges(*T, charge_pos, (hipStream_t)stream);
+  });
+}
+
+int bemfmm_tree_destroy(bemfmm_tree *tree) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    (void)hipDeviceSynchronize();
+    delete T;
+  });
+}
+
+int bemfmm_tree_get_info(const bemfmm_tree *tree, bemfmm_tree_info *info) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    need(info != nullptr, "info is NULL");
+    bemfmm_tree_info I{};
+    I.n_panels = T->N;
+    I.n_charges = T->Q;
+    I.leaf_level = T->L;
+    I.n_cells = T->ncell_tot;
+    I.n_leaves = T->ncell[T->L];
+    I.n_near_pairs = T->n_near_leaf;
+    I.n_far_pairs = T->nfar;
+    I.n_offsets = T->tab ? T->tab->noff() : 0;
+    I.p2p_pairs_panels = T->p2p_pairs_pp;
+    for (int d = 0; d < 3; ++d) I.lo[d] = T->lo[d];
+    I.side = T->side;
+    *info = I;
+  });
+}
+
+int bemfmm_fmm_matvec(bemfmm_tree *tree, int op, int precision, const double *x, double *y, void *stream) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    need(op >= BEMFMM_OP_A && op <= BEMFMM_OP_CT, "unknown operator");
+    need(precision >= BEMFMM_FP64 && precision <= BEMFMM_FP32_REFINED, "unknown precision");
+    need(x && y, "x/y are NULL");
+    op_apply(*T, op, precision, x, y, (hipStream_t)stream);
+  });
+}
+
+int bemfmm_solve_bem(bemfmm_tree *tree, const double *q, double *x, double tol, int maxit, int restart,
+                     int precision, bemfmm_solve_info *info, void *stream) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    need(precision >= BEMFMM_FP64 && precision <= BEMFMM_FP32_REFINED, "unknown precision");
+    need(x != nullptr && (T->Q == 0 || q != nullptr), "q/x are NULL");
+    need(tol > 0 && maxit >= 1, "tol must be > 0 and maxit >= 1");
+    solve_bem(*T, q, x, tol, maxit, restart, precision, info, (hipStream_t)stream);
+  });
+}
+
+int bemfmm_bibee_energy(bemfmm_tree *tree, const double *q, int kind, int precision, double *dG_host,
+                        void *stream) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    need(kind == BEMFMM_BIBEE_CFA || kind == BEMFMM_BIBEE_P, "unknown BIBEE kind");
+    need(dG_host != nullptr && (T->Q == 0 || q != nullptr), "q/dG are NULL");
+    *dG_host = bibee(*T, q, kind, precision, (hipStream_t)stream);
+  });
+}
+
+int bemfmm_solvation_energy(bemfmm_tree *tree, const double *q, const double *x, int precision, double *dG_host,
+                            void *stream) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    need(dG_host != nullptr && x != nullptr && (T->Q == 0 || q != nullptr), "q/x/dG are NULL");
+    *dG_host = energy(*T, q, x, precision, (hipStream_t)stream);
+  });
+}
+
+int bemfmm_adjoint_grad(bemfmm_tree *tree, const double *q, const double *x, double tol, int maxit, int restart,
+                        int precision, double *dG_dq, double *dG_dpos, bemfmm_solve_info *info, void *stream) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    need(x != nullptr && (T->Q == 0 || q != nullptr), "q/x are NULL");
+    need(tol > 0 && maxit >= 1, "tol must be > 0 and maxit >= 1");
+    adjoint(*T, q, x, tol, maxit, restart, precision, dG_dq, dG_dpos, info, (hipStream_t)stream);
+  });
+}
+
+const char *bemfmm_last_error(void) { return g_err.c_str(); }
+
+int bemfmm_tree_export(const bemfmm_tree *tree, int32_t *panel_perm, int32_t *charge_perm, uint32_t *panel_key,
+                       uint32_t *charge_key, uint32_t *cell_key, int32_t *cell_level, int32_t *cell_range,
+                       int32_t *cell_parent, int32_t *near_ptr, int32_t *near_idx, int32_t *far_pairs) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    const int L = T->L;
+    auto d2h = [&](void *dst, const void *src, size_t bytes) {
+      if (dst && bytes) HIP_OK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+    };
+    d2h(panel_perm, T->pperm.p, T->N * 4);
+    d2h(panel_key, T->pkey.p, T->N * 4);
+    d2h(charge_perm, T->qperm.p, T->Q * 4);
+    d2h(charge_key, T->qkey.p, T->Q * 4);
+    d2h(cell_key, T->ckey.p, T->ncell_tot * 4);
+    d2h(cell_level, T->clevel.p, T->ncell_tot * 4);
+    d2h(cell_range, T->crange.p, T->ncell_tot * 16);
+    d2h(cell_parent, T->cparent.p, T->ncell_tot * 4);
+    d2h(near_ptr, T->near_ptr.p + T->near_ptr_off[L], ((size_t)T->ncell[L] + 1) * 4);
+    d2h(near_idx, T->near_idx.p + T->near_off[L], T->n_near_leaf * 4);
+    if (far_pairs && T->nfar) {
+      std::vector<int2> ts(T->nfar);
+      d2h(ts.data(), T->far_ts.p, T->nfar * sizeof(int2));
+      std::vector<int32_t> lev(T->ncell_tot);
+      for (int l = 0; l <= L; ++l)
+        for (int64_t i = T->coff[l]; i < T->coff[l + 1]; ++i) lev[i] = l;
+      for (int64_t k = 0; k < T->nfar; ++k) {
+        const int l = lev[ts[k].x];
+        far_pairs[3 * k] = l;
+        far_pairs[3 * k + 1] = ts[k].x - (int32_t)T->coff[l];
+        far_pairs[3 * k + 2] = ts[k].y - (int32_t)T->coff[l];
+      }
+    }
+  });
+}
+
+int bemfmm_debug_expansions(bemfmm_tree *tree, int precision, int which, double *out_host) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    need(out_host != nullptr, "out is NULL");
+    HIP_OK(hipDeviceSynchronize());
+    debug_expansions(*T, precision, which, out_host, nullptr);
+  });
+}
+
+int bemfmm_debug_fields(bemfmm_tree *tree, int precision, double *near_host, double *far_host) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    HIP_OK(hipDeviceSynchronize());
+    debug_fields(*T, precision, near_host, far_host, nullptr);
+  });
+}
+
+int bemfmm_profile(bemfmm_tree *tree, int enable, int reset) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    T->prof = enable != 0;
+    if (reset)
+      for (int i = 0; i < 6; ++i) {
+        T->prof_ms[i] = 0;
+        T->prof_cnt[i] = 0;
+      }
+  });
+}
+
+int bemfmm_profile_get(bemfmm_tree *tree, const char *stage, double *ms_host, int64_t *count_host) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    static const char *names[6] = {"p2m", "m2m", "m2l", "l2l", "p2p", "other"};
+    int k = -1;
+    for (int i = 0; i < 6; ++i)
+      if (stage && std::strcmp(stage, names[i]) == 0) k = i;
+    need(k >= 0, "unknown stage");
+    if (ms_host) *ms_host = T->prof_ms[k];
+    if (count_host) *count_host = T->prof_cnt[k];
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,254 @@
+// Internal declarations of the bemfmm library (gfx950 / MI355X).
+//
+// Layout in HBM (all library-owned, allocated at tree build):
+//   * panels and charges are kept in Morton order; every per-point array
+//     below is indexed by the sorted position;
+//   * positions are stored relative to the centre of the point's leaf cell
+//     (FP32 and FP64 copies), so FP32 differences inside the near field do
+//     not lose digits to the absolute coordinate;
+//   * cells of all levels live in one global array, level by level, each
+//     level in increasing Morton prefix;
+//   * expansions are [cells x PS] (PS = p^2 rounded up to a multiple of 16,
+//     zero padded), one array per precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "../../include/bemfmm.h"
+
+namespace bemfmm {
+
+constexpr int KEY_BITS = 10;  // bits per axis of the Morton keys (30-bit keys)
+constexpr int LMAX = KEY_BITS;
+constexpr int PMAX = 12;
+constexpr double PI = 3.14159265358979323846;
+constexpr double K_COULOMB = 332.06;
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+void set_error(const std::string &msg);
+
+#define BF_THROW(code_, msg_)                                                     \
+  do {                                                                            \
+    throw ::bemfmm::Error{(code_), std::string(msg_)};                            \
+  } while (0)
+
+#define HIP_OK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      BF_THROW(e_ == hipErrorOutOfMemory ? BEMFMM_ENOMEM : BEMFMM_EDEVICE,        \
+               std::string(#expr) + ": " + hipGetErrorString(e_) + " (" __FILE__ ")"); \
+  } while (0)
+
+#define LAUNCH_OK() HIP_OK(hipGetLastError())
+
+// Owning device buffer.
+template <class T>
+struct DBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    if (count == n && p) return;
+    release();
+    if (count == 0) return;
+    HIP_OK(hipMalloc((void **)&p, count * sizeof(T)));
+    n = count;
+  }
+  // grow only
+  void reserve(size_t count) {
+    if (count > n) alloc(count);
+  }
+  void zero(hipStream_t s) {
+    if (p) HIP_OK(hipMemsetAsync(p, 0, n * sizeof(T), s));
+  }
+  T *get() const { return p; }
+};
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+inline int pad16(int v) { return (v + 15) / 16 * 16; }
+
+// Packed index of Re(n, m) (m >= 0) / Im(n, m) (m >= 1) in a p^2 vector.
+__host__ __device__ inline int idx_re(int n, int m) { return m == 0 ? n * n : n * n + 2 * m - 1; }
+__host__ __device__ inline int idx_im(int n, int m) { return n * n + 2 * m; }
+
+// ---------------------------------------------------------------- tables
+
+// FP64 translation operators for order p and a MAC (host-built, cached).
+struct Tables {
+  int p = 0, ps = 0;
+  double theta = 0;
+  int mac = 0;
+  int R = 0;                       // offsets lie in [-R, R]^3
+  std::vector<int> offset_id;      // (2R+1)^3 -> compact id or -1
+  std::vector<int> offsets;        // compact id -> (ox, oy, oz)
+  std::vector<double> m2l;         // [noff][ps][ps] (row = output, col = input)
+  std::vector<double> m2m;         // [8][ps][ps]  child octant -> parent
+  std::vector<double> l2l;         // [8][ps][ps]  parent -> child octant
+  int noff() const { return (int)offsets.size() / 3; }
+};
+
+const Tables &get_tables(int p, double theta, int mac);
+bool mac_far_host(int ox, int oy, int oz, double theta, int mac);
+
+// ---------------------------------------------------------------- tree
+
+struct PrecBufs;  // per-precision FMM buffers (fmm.hip)
+
+struct Tree {
+  int magic = 0x5eedbe11;
+  int device = 0;
+  bemfmm_params prm{};
+  int p = 10, ps = 112;
+  int64_t N = 0, Q = 0;
+  int L = 0;
+  double lo[3] = {0, 0, 0};
+  double side = 1;
+  std::vector<int> ncell;       // per level
+  std::vector<int64_t> coff;    // per level offset into global cell arrays (size L+2)
+  int64_t ncell_tot = 0;
+
+  // user-order geometry (FP64)
+  DBuf<double> c, nrm, area;  // 3N, 3N, N
+  DBuf<double> qpos;          // 3Q user-order charge positions (current)
+
+  // Morton order
+  DBuf<int32_t> pperm, qperm;     // sorted -> user
+  DBuf<int32_t> pinv, qinv;       // user -> sorted
+  DBuf<uint32_t> pkey, qkey;      // sorted keys
+  DBuf<int32_t> pleaf, qleaf;     // leaf (level-L local) index of each sorted point
+
+  // sorted point data, leaf-relative
+  DBuf<float4> p32pos, p32nrm;    // (rx, ry, rz, area), (nx, ny, nz, 0)
+  DBuf<double4> p64pos, p64nrm;
+  DBuf<float4> q32pos;            // (rx, ry, rz, 0)
+  DBuf<double4> q64pos;
+
+  // cells (global over levels)
+  DBuf<uint32_t> ckey;    // level prefix
+  DBuf<int32_t> clevel;
+  DBuf<int4> crange;      // panel begin, end, charge begin, end
+  DBuf<int32_t> cparent;  // global index (-1 root)
+  DBuf<int2> cchild;      // global child range [b, e)
+  DBuf<int32_t> cxyz;     // packed integer coords x | y << 10 | z << 20
+
+  // lists
+  std::vector<int64_t> near_off;     // per level offsets into near_idx (levels 0..L), size L+2
+  DBuf<int32_t> near_ptr;            // per level CSR, concatenated: [sum (ncell_l + 1)]
+  std::vector<int64_t> near_ptr_off; // per level offset into near_ptr
+  DBuf<int32_t> near_idx;            // level-local source cells
+  int64_t n_near_leaf = 0;
+
+  std::vector<int64_t> far_off;      // per level offsets into far pairs (size L+2)
+  int64_t nfar = 0;
+  DBuf<int2> far_ts;                 // (target, source) level-local, target-major per level
+  DBuf<int32_t> far_ptr;             // per-level target CSR into far pairs (global pair index), [ncell_tot + 1]
+  DBuf<int32_t> far_order;           // pair indices sorted by (level, offset id)
+  DBuf<int32_t> m2l_tile_group;      // per MFMA tile: group index
+  DBuf<int32_t> m2l_tile_row;        // per tile: first row (position in far_order)
+  DBuf<int32_t> m2l_group_off;       // per group: compact offset id
+  DBuf<int32_t> m2l_group_end;       // per group: end position in far_order
+  int64_t n_m2l_tiles = 0, n_m2l_groups = 0;
+  int64_t p2p_pairs_pp = 0;
+
+  // translation tables on the device (FP32 MFMA-swizzled M2L; FP64 too)
+  const Tables *tab = nullptr;
+  DBuf<float> t_m2l32;   // [noff][PS/4 kk][PS/16 ct][64 lanes]
+  DBuf<double> t_m2l64;  // same layout
+  DBuf<float> t_m2m32, t_l2l32;   // [8][ps in][ps out] (transposed: lanes read rows)
+  DBuf<double> t_m2m64, t_l2l64;
+
+  // P2P work decomposition: (leaf, first sorted index) per 64-target chunk
+  DBuf<int2> chunk_p, chunk_q;
+  int64_t nchunk_p = 0, nchunk_q = 0;
+
+  PrecBufs *pb32 = nullptr, *pb64 = nullptr;
+
+  // solver scratch (FP64, user order)
+  DBuf<double> wrk;      // general vectors
+  DBuf<double> gm_V;     // GMRES basis
+  DBuf<double> red;      // reduction scratch
+  DBuf<double> hred;     // pinned? (device) dot results
+
+  // stage profiling
+  bool prof = false;
+  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+  int64_t prof_cnt[6] = {0, 0, 0, 0, 0, 0};
+  hipEvent_t ev[12] = {};
+  bool ev_init = false;
+
+  int last_op32 = -1, last_op64 = -1;
+
+  ~Tree();
+};
+
+Tree *check_tree(const bemfmm_tree *t);
+
+// tree_build.hip
+void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                const double *qpos, int64_t nq, hipStream_t s);
+void set_charges(Tree &T, const double *qpos, hipStream_t s);
+void upload_tables(Tree &T, hipStream_t s);
+
+// primitives (tree_build.hip)
+void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, int32_t *total_host);
+void radix_sort_u32(uint32_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
+
+// fmm.hip
+enum SrcKind { SRC_PANEL_MONO = 0, SRC_PANEL_DIP = 1, SRC_PANEL_MONODIP = 2, SRC_CHARGE_MONO = 3 };
+enum TgtKind { TGT_PANEL = 0, TGT_CHARGE = 1 };
+enum OutKind { OUT_POT = 0, OUT_NGRAD = 1, OUT_POTGRAD = 2 };
+
+struct FmmRequest {
+  int src;          // SrcKind
+  int tgt;          // TgtKind
+  int out;          // OutKind
+  const double *wmono;  // user-order monopole weights (panels: multiplied by area inside) or NULL
+  const double *wdip;   // user-order dipole strengths (along panel normals) or NULL
+  bool mono_area;       // panel monopoles: weight = area * wmono
+  // epilogue: y[user] = alpha * xin[user] + beta * (area_scale ? a : 1) * field / (4 pi)
+  const double *xin;
+  double alpha, beta;
+  bool area_scale;
+  double *y;            // OUT_POT/NGRAD: [n_targets]; OUT_POTGRAD: [n_targets*4] (pot, gx, gy, gz)
+  bool accumulate;      // y += instead of y =
+};
+
+void fmm_apply(Tree &T, int precision, const FmmRequest &rq, hipStream_t s);
+void fmm_free(Tree &T);
+void debug_expansions(Tree &T, int precision, int which, double *out_host, hipStream_t s);
+void debug_fields(Tree &T, int precision, double *near_host, double *far_host, hipStream_t s);
+
+// solve.hip
+void op_apply(Tree &T, int op, int precision, const double *x, double *y, hipStream_t s);
+void solve_bem(Tree &T, const double *q, double *x, double tol, int maxit, int restart, int precision,
+               bemfmm_solve_info *info, hipStream_t s);
+double energy(Tree &T, const double *q, const double *x, int precision, hipStream_t s);
+double bibee(Tree &T, const double *q, int kind, int precision, hipStream_t s);
+void adjoint(Tree &T, const double *q, const double *x, double tol, int maxit, int restart, int precision,
+             double *dq, double *dpos, bemfmm_solve_info *info, hipStream_t s);
+double dot_d(Tree &T, const double *a, const double *b, int64_t n, hipStream_t s);
+
+// profiling helpers (fmm.hip)
+enum Stage { ST_P2M = 0, ST_M2M = 1, ST_M2L = 2, ST_L2L = 3, ST_P2P = 4, ST_OTHER = 5 };
+void prof_begin(Tree &T, int stage, hipStream_t s);
+void prof_end(Tree &T, int stage, hipStream_t s);
+
+}  // namespace bemfmm

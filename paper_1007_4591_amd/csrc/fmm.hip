@@ -1,0 +1,963 @@
+// Fast-multipole evaluation (Section 2.3) on gfx950: one pass of
+//   pack sources -> P2M (leaves) -> M2M (levels L-1..2) -> M2L (all levels,
+//   grouped by translation offset, dense contractions on MFMA) ->
+//   downward pass (ordered reduction of M2L results + L2L, levels 2..L) ->
+//   P2P near field fused with L2P and the operator's final combination.
+//
+// Every stage is templated on the working precision (float or double); the
+// FP32 path uses v_mfma_f32_16x16x4f32 for M2L and v_rsq_f32 in P2P, the
+// FP64 path v_mfma_f64_16x16x4f64 and a refined FP64 reciprocal square root.
+// Accumulation orders are fixed (no floating-point atomics), so results are
+// reproducible run to run.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace bemfmm {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <class R> struct V4;
+template <> struct V4<float> { using T = float4; };
+template <> struct V4<double> { using T = double4; };
+
+struct PrecBufs {
+  int prec = 0;  // 0 = FP64, 1 = FP32
+  DBuf<char> src_pos, src_dip;  // real4 [max(N, Q)]
+  DBuf<char> M, L;              // real [ncell_tot * ps]
+  DBuf<char> m2l_out;           // real [nfar * ps]
+  DBuf<char> E;                 // real [nleaf * 4 * ps]
+  DBuf<double> dbg_near, dbg_far;  // sorted-order raw fields (debug)
+  int last_tgt = 0;
+  bool have = false;
+};
+
+namespace {
+
+__constant__ float c_rec1_f[PMAX + 1][PMAX + 1];  // (2n-1)/(n^2-m^2)
+__constant__ float c_rec2_f[PMAX + 1][PMAX + 1];  // 1/(n^2-m^2)
+__constant__ double c_rec1_d[PMAX + 1][PMAX + 1];
+__constant__ double c_rec2_d[PMAX + 1][PMAX + 1];
+__constant__ float c_half_inv_m_f[PMAX + 1];      // 1/(2m)
+__constant__ double c_half_inv_m_d[PMAX + 1];
+
+template <class R> __device__ inline R rec1(int n, int m);
+template <> __device__ inline float rec1<float>(int n, int m) { return c_rec1_f[n][m]; }
+template <> __device__ inline double rec1<double>(int n, int m) { return c_rec1_d[n][m]; }
+template <class R> __device__ inline R rec2(int n, int m);
+template <> __device__ inline float rec2<float>(int n, int m) { return c_rec2_f[n][m]; }
+template <> __device__ inline double rec2<double>(int n, int m) { return c_rec2_d[n][m]; }
+template <class R> __device__ inline R hinv(int m);
+template <> __device__ inline float hinv<float>(int m) { return c_half_inv_m_f[m]; }
+template <> __device__ inline double hinv<double>(int m) { return c_half_inv_m_d[m]; }
+
+__device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rsq(double x) { return rsqrt(x); }
+
+// Regular solid harmonics R_n^m(x, y, z) for 0 <= m <= n < p, generated in
+// m-major order by the recurrences documented with the host tables; calls
+// f(n, m, Re, Im) once per pair.
+template <class R, class F>
+__device__ inline void regular_harmonics(int p, R x, R y, R z, F &&f) {
+  const R r2 = x * x + y * y + z * z;
+  R dr = R(1), di = R(0);
+  for (int m = 0; m < p; ++m) {
+    if (m > 0) {
+      const R c = -hinv<R>(m);
+      const R nr = c * (x * dr - y * di);
+      const R ni = c * (x * di + y * dr);
+      dr = nr;
+      di = ni;
+    }
+    f(m, m, dr, di);
+    if (m + 1 < p) {
+      R pr = dr, pi = di;
+      R qr = z * dr, qi = z * di;
+      f(m + 1, m, qr, qi);
+      for (int n = m + 2; n < p; ++n) {
+        const R a = rec1<R>(n, m) * z, b = rec2<R>(n, m) * r2;
+        const R nr = a * qr - b * pr;
+        const R ni = a * qi - b * pi;
+        f(n, m, nr, ni);
+        pr = qr;
+        pi = qi;
+        qr = nr;
+        qi = ni;
+      }
+    }
+  }
+}
+
+__device__ inline void xyz_of(int32_t v, int &x, int &y, int &z) {
+  x = v & 1023;
+  y = (v >> 10) & 1023;
+  z = (v >> 20) & 1023;
+}
+
+// ------------------------------------------------------------ pack sources
+
+// src_pos[i] = (rx, ry, rz, w) in sorted order; src_dip[i] = d * n (moment)
+template <class R>
+__global__ void k_pack_panels(int64_t N, const int32_t *__restrict__ perm, const typename V4<R>::T *__restrict__ pos,
+                              const typename V4<R>::T *__restrict__ nrm, const double *__restrict__ area,
+                              const double *__restrict__ wmono, int mono_area, const double *__restrict__ wdip,
+                              typename V4<R>::T *__restrict__ out_pos, typename V4<R>::T *__restrict__ out_dip) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int64_t u = perm[i];
+  typename V4<R>::T p = pos[i];
+  R w = R(0);
+  if (wmono) {
+    double wd = wmono[u];
+    if (mono_area) wd *= area[u];
+    w = (R)wd;
+  }
+  typename V4<R>::T o;
+  o.x = p.x;
+  o.y = p.y;
+  o.z = p.z;
+  o.w = w;
+  out_pos[i] = o;
+  if (wdip) {
+    typename V4<R>::T n = nrm[i];
+    R d = (R)wdip[u];
+    typename V4<R>::T m;
+    m.x = d * n.x;
+    m.y = d * n.y;
+    m.z = d * n.z;
+    m.w = R(0);
+    out_dip[i] = m;
+  }
+}
+
+template <class R>
+__global__ void k_pack_charges(int64_t Q, const int32_t *__restrict__ perm, const typename V4<R>::T *__restrict__ pos,
+                               const double *__restrict__ q, typename V4<R>::T *__restrict__ out_pos) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Q) return;
+  typename V4<R>::T p = pos[i];
+  p.w = (R)q[perm[i]];
+  out_pos[i] = p;
+}
+
+// -------------------------------------------------------------------- P2M
+
+// One wave per leaf: each lane accumulates its sources' contributions in a
+// private LDS row (stride ps + 1 avoids bank conflicts), then lanes sum the
+// columns in lane order.  Monopoles add w conj(R_n^m(rho)); dipoles add
+// mu . grad conj(R_n^m) = mu_z conj(R_{n-1}^m) + (mu_x + i mu_y)/2 conj(R_{n-1}^{m+1})
+//                        - (mu_x - i mu_y)/2 conj(R_{n-1}^{m-1}),
+// with R_{n-1}^{-1} = -conj(R_{n-1}^1); rho and mu are in units of the leaf side.
+template <class R, bool MONO, bool DIP>
+__global__ void __launch_bounds__(64) k_p2m(int p, int ps, int64_t C, const int4 *__restrict__ range, int charges,
+                                            const typename V4<R>::T *__restrict__ src,
+                                            const typename V4<R>::T *__restrict__ dip, R inv_s,
+                                            R *__restrict__ M) {
+  extern __shared__ char smem_raw[];
+  R *row = reinterpret_cast<R *>(smem_raw);
+  const int lane = threadIdx.x;
+  const int stride = ps + 1;
+  const int64_t c = blockIdx.x;
+  if (c >= C) return;
+  R *my = row + lane * stride;
+  for (int k = 0; k < ps; ++k) my[k] = R(0);
+  const int4 rg = range[c];
+  const int b = charges ? rg.z : rg.x, e = charges ? rg.w : rg.y;
+  for (int j0 = b; j0 < e; j0 += 64) {
+    const int j = j0 + lane;
+    if (j < e) {
+      const typename V4<R>::T sp = src[j];
+      const R x = sp.x * inv_s, y = sp.y * inv_s, z = sp.z * inv_s;
+      const R w = sp.w;
+      R mx = R(0), myy = R(0), mz = R(0);
+      if (DIP) {
+        const typename V4<R>::T mo = dip[j];
+        mx = mo.x * inv_s;
+        myy = mo.y * inv_s;
+        mz = mo.z * inv_s;
+      }
+      regular_harmonics<R>(p, x, y, z, [&](int n, int m, R re, R im) {
+        if (MONO) {
+          my[idx_re(n, m)] += w * re;
+          if (m > 0) my[idx_im(n, m)] -= w * im;
+        }
+        if (DIP && n <= p - 2) {
+          const int no = n + 1;
+          my[idx_re(no, m)] += mz * re;
+          if (m > 0) my[idx_im(no, m)] -= mz * im;
+          if (m >= 1) {
+            const R hr = R(0.5) * (mx * re + myy * im);
+            if (m == 1) {
+              my[idx_re(no, 0)] += hr + hr;
+            } else {
+              my[idx_re(no, m - 1)] += hr;
+              my[idx_im(no, m - 1)] += R(0.5) * (myy * re - mx * im);
+            }
+          }
+          my[idx_re(no, m + 1)] -= R(0.5) * (mx * re - myy * im);
+          my[idx_im(no, m + 1)] += R(0.5) * (mx * im + myy * re);
+        }
+      });
+    }
+  }
+  __syncthreads();
+  R *out = M + c * ps;
+  for (int k = lane; k < ps; k += 64) {
+    R acc = R(0);
+    for (int l = 0; l < 64; ++l) acc += row[l * stride + k];
+    out[k] = acc;
+  }
+}
+
+// -------------------------------------------------------------------- M2M
+
+// One wave per parent cell at one level: M(parent) = sum over children of
+// S_oct M(child); S stored transposed [oct][in][out] so lanes read rows.
+template <class R>
+__global__ void __launch_bounds__(64) k_m2m(int np2, int ps, int64_t c0, int64_t C, const int2 *__restrict__ child,
+                                            const uint32_t *__restrict__ ckey, const R *__restrict__ St,
+                                            R *__restrict__ M) {
+  const int64_t c = c0 + blockIdx.x;
+  if (blockIdx.x >= C) return;
+  const int lane = threadIdx.x;
+  const int2 ch = child[c];
+  R acc0 = R(0), acc1 = R(0), acc2 = R(0);
+  for (int cc = ch.x; cc < ch.y; ++cc) {
+    const int oct = ckey[cc] & 7;
+    const R *S = St + (size_t)oct * ps * ps;
+    const R *Mc = M + (size_t)cc * ps;
+    for (int j = 0; j < np2; ++j) {
+      const R mj = Mc[j];
+      acc0 += S[(size_t)j * ps + lane] * mj;
+      if (lane + 64 < ps) acc1 += S[(size_t)j * ps + lane + 64] * mj;
+      if (lane + 128 < ps) acc2 += S[(size_t)j * ps + lane + 128] * mj;
+    }
+  }
+  R *out = M + (size_t)c * ps;
+  out[lane] = acc0;
+  if (lane + 64 < ps) out[lane + 64] = acc1;
+  if (lane + 128 < ps) out[lane + 128] = acc2;
+}
+
+// -------------------------------------------------------------------- M2L
+
+// Offset-grouped dense M2L on MFMA.  Work tile = 64 consecutive pairs of one
+// offset group (4 waves x 16 pairs).  For each wave:
+//   D[16 pairs x 16*NT outputs] = A[16 x ps] * B[ps x 16*NT],
+// A = gathered source expansions, B = T_o^T, with the K dimension permuted
+// so that each lane reads a contiguous quarter of its source row:
+// at k-step kk, lane group g = lane/16 supplies input g*KK + kk.
+// Results go to per-pair slots (target-major order), reduced later in a
+// fixed order.
+template <int NT>
+__global__ void __launch_bounds__(256) k_m2l_f32(const int32_t *__restrict__ tile_group,
+                                                 const int32_t *__restrict__ tile_row,
+                                                 const int32_t *__restrict__ group_off,
+                                                 const int32_t *__restrict__ group_end,
+                                                 const int32_t *__restrict__ order, const int2 *__restrict__ ts,
+                                                 const float *__restrict__ Tsw, const float *__restrict__ M,
+                                                 float *__restrict__ out) {
+  constexpr int PS = NT * 16;
+  constexpr int KK = PS / 4;
+  const int tile = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = tile_group[tile];
+  const int end = group_end[g];
+  const int row0 = tile_row[tile] + wave * 16;
+  if (row0 >= end) return;
+  const int off = group_off[g];
+  const int i = lane & 15, kq = lane >> 4;
+  // A operand: this lane's quarter of its pair's source row
+  float a[KK];
+  const int r = row0 + i;
+  if (r < end) {
+    const int pair = order[r];
+    const int src = ts[pair].y;
+    const float4 *Ms = reinterpret_cast<const float4 *>(M + (size_t)src * PS + kq * KK);
+#pragma unroll
+    for (int v = 0; v < KK / 4; ++v) {
+      const float4 t = Ms[v];
+      a[4 * v] = t.x;
+      a[4 * v + 1] = t.y;
+      a[4 * v + 2] = t.z;
+      a[4 * v + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < KK; ++v) a[v] = 0.f;
+  }
+  f32x4 acc[NT];
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const float *B = Tsw + (size_t)off * KK * NT * 64 + lane;
+#pragma unroll
+  for (int kk = 0; kk < KK; ++kk) {
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) {
+      const float b = B[(kk * NT + ct) * 64];
+      acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b, acc[ct], 0, 0, 0);
+    }
+  }
+  // D[row = 4*(lane/16) + q][col = ct*16 + lane%16]
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int rr = row0 + 4 * kq + q;
+    if (rr < end) {
+      float *o = out + (size_t)order[rr] * PS + i;
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) o[ct * 16] = acc[ct][q];
+    }
+  }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_m2l_f64(const int32_t *__restrict__ tile_group,
+                                                 const int32_t *__restrict__ tile_row,
+                                                 const int32_t *__restrict__ group_off,
+                                                 const int32_t *__restrict__ group_end,
+                                                 const int32_t *__restrict__ order, const int2 *__restrict__ ts,
+                                                 const double *__restrict__ Tsw, const double *__restrict__ M,
+                                                 double *__restrict__ out) {
+  constexpr int PS = NT * 16;
+  constexpr int KK = PS / 4;
+  const int tile = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = tile_group[tile];
+  const int end = group_end[g];
+  const int row0 = tile_row[tile] + wave * 16;
+  if (row0 >= end) return;
+  const int off = group_off[g];
+  const int i = lane & 15, kq = lane >> 4;
+  const int r = row0 + i;
+  const double *Ms = nullptr;
+  if (r < end) Ms = M + (size_t)ts[order[r]].y * PS + kq * KK;
+  f64x4 acc[NT];
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct) acc[ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const double *B = Tsw + (size_t)off * KK * NT * 64 + lane;
+  for (int kk = 0; kk < KK; ++kk) {
+    const double av = Ms ? Ms[kk] : 0.0;
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) {
+      const double b = B[(kk * NT + ct) * 64];
+      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[ct], 0, 0, 0);
+    }
+  }
+  // FP64 layout: D[row = lane/16 + 4*q][col = ct*16 + lane%16]
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int rr = row0 + kq + 4 * q;
+    if (rr < end) {
+      double *o = out + (size_t)order[rr] * PS + i;
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) o[ct * 16] = acc[ct][q];
+    }
+  }
+}
+
+// ----------------------------------------------------------- downward pass
+
+// One wave per cell of level l: L = L2L(parent) + sum of its M2L results in
+// pair order (compensated).  At the leaf level also writes the evaluation
+// coefficients E[leaf][4][ps] for potential and gradient (see L2P below).
+template <class R>
+__global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int64_t C, int with_parent,
+                                                 const int32_t *__restrict__ parent, const uint32_t *__restrict__ ckey,
+                                                 const R *__restrict__ St, const int32_t *__restrict__ far_ptr,
+                                                 const R *__restrict__ m2l, R *__restrict__ Lx, int leaf,
+                                                 R inv_s, R *__restrict__ E) {
+  extern __shared__ char smem_raw[];
+  R *Ls = reinterpret_cast<R *>(smem_raw);
+  const int64_t c = c0 + blockIdx.x;
+  if (blockIdx.x >= C) return;
+  const int lane = threadIdx.x;
+  const int np2 = p * p;
+  R s[3] = {R(0), R(0), R(0)}, comp[3] = {R(0), R(0), R(0)};
+  const int b = far_ptr[c], e = far_ptr[c + 1];
+  for (int q = b; q < e; ++q) {
+    const R *src = m2l + (size_t)q * ps;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int k = lane + 64 * t;
+      if (k < ps) {
+        const R y = src[k] - comp[t];
+        const R tt = s[t] + y;
+        comp[t] = (tt - s[t]) - y;
+        s[t] = tt;
+      }
+    }
+  }
+  if (with_parent) {
+    const int pc = parent[c];
+    const int oct = ckey[c] & 7;
+    const R *S = St + (size_t)oct * ps * ps;
+    const R *Lp = Lx + (size_t)pc * ps;
+    R a[3] = {R(0), R(0), R(0)};
+    for (int j = 0; j < np2; ++j) {
+      const R lj = Lp[j];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int k = lane + 64 * t;
+        if (k < ps) a[t] += S[(size_t)j * ps + k] * lj;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) s[t] += a[t];
+  }
+  R *out = Lx + (size_t)c * ps;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const int k = lane + 64 * t;
+    if (k < ps) {
+      out[k] = s[t];
+      Ls[k] = s[t];
+    }
+  }
+  if (!leaf) return;
+  __syncthreads();
+  // evaluation coefficients of the leaf (scaled to physical units):
+  // phi(x) = sum_k E0[k] * Rpacked_k(rho), grad phi = sum_k E{x,y,z}[k] * Rpacked_k(rho)
+  R *Ec = E + (size_t)blockIdx.x * 4 * ps;
+  const R inv_s2 = inv_s * inv_s;
+  for (int k = lane; k < ps; k += 64) {
+    Ec[k] = R(0);
+    Ec[ps + k] = R(0);
+    Ec[2 * ps + k] = R(0);
+    Ec[3 * ps + k] = R(0);
+  }
+  __syncthreads();
+  auto Lre = [&](int n, int m) -> R {  // Re L_n^m for any m
+    if (n >= p || m > n || -m > n) return R(0);
+    if (m >= 0) return Ls[idx_re(n, m)];
+    return ((-m) & 1) ? -Ls[idx_re(n, -m)] : Ls[idx_re(n, -m)];
+  };
+  auto Lim = [&](int n, int m) -> R {
+    if (n >= p || m > n || -m > n || m == 0) return R(0);
+    if (m > 0) return Ls[idx_im(n, m)];
+    // L^{-m} = (-1)^m conj(L^m)
+    return ((-m) & 1) ? Ls[idx_im(n, -m)] : -Ls[idx_im(n, -m)];
+  };
+  for (int k = lane; k < np2; k += 64) {
+    // decode k -> (n, m, part)
+    int n = 0;
+    while ((n + 1) * (n + 1) <= k) ++n;
+    const int rem = k - n * n;
+    const int m = (rem + 1) / 2;
+    const bool im = (rem > 0) && ((rem & 1) == 0);
+    const R two = (m > 0) ? R(2) : R(1);
+    // potential
+    Ec[k] = im ? (-R(2) * Lim(n, m) * inv_s) : (two * Lre(n, m) * inv_s);
+    if (n <= p - 2) {
+      // G_z = L_{n+1}^m; G_x = (L_{n+1}^{m-1} - L_{n+1}^{m+1})/2; G_y = -i (L_{n+1}^{m+1} + L_{n+1}^{m-1})/2
+      const R gzr = Lre(n + 1, m), gzi = Lim(n + 1, m);
+      const R gxr = R(0.5) * (Lre(n + 1, m - 1) - Lre(n + 1, m + 1));
+      const R gxi = R(0.5) * (Lim(n + 1, m - 1) - Lim(n + 1, m + 1));
+      const R sr = R(0.5) * (Lre(n + 1, m + 1) + Lre(n + 1, m - 1));
+      const R si = R(0.5) * (Lim(n + 1, m + 1) + Lim(n + 1, m - 1));
+      const R gyr = si, gyi = -sr;  // -i (sr + i si)
+      if (im) {
+        Ec[ps + k] = -R(2) * gxi * inv_s2;
+        Ec[2 * ps + k] = -R(2) * gyi * inv_s2;
+        Ec[3 * ps + k] = -R(2) * gzi * inv_s2;
+      } else {
+        Ec[ps + k] = two * gxr * inv_s2;
+        Ec[2 * ps + k] = two * gyr * inv_s2;
+        Ec[3 * ps + k] = two * gzr * inv_s2;
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------- P2P + L2P
+
+// One source-target pair.  Monopole: lp += w/r, (lx,ly,lz) += w d/r^3 (=
+// -grad).  Dipole m: lp += m.d/r^3, (lx,ly,lz) += 3 (m.d) d/r^5 - m/r^3 (=
+// -grad).  d = target - source, ri = 1/r (0 for the excluded self pair).
+template <class R, int SRC, int OUT>
+__device__ __forceinline__ void pair_accumulate(const typename V4<R>::T &s4, const typename V4<R>::T *sdip, int j,
+                                                R dx, R dy, R dz, R ri, R &lp, R &lx, R &ly, R &lz) {
+  if (SRC == SRC_PANEL_MONO || SRC == SRC_CHARGE_MONO) {
+    const R wr = s4.w * ri;
+    if (OUT == OUT_POT || OUT == OUT_POTGRAD) lp += wr;
+    if (OUT != OUT_POT) {
+      const R t = wr * ri * ri;
+      lx += t * dx;
+      ly += t * dy;
+      lz += t * dz;
+    }
+  } else {
+    const typename V4<R>::T m4 = sdip[j];
+    const R ri2 = ri * ri;
+    const R ri3 = ri2 * ri;
+    const R md = m4.x * dx + m4.y * dy + m4.z * dz;
+    R t = R(0), pot = md * ri3;
+    if (SRC == SRC_PANEL_MONODIP) {
+      const R wr = s4.w * ri;
+      pot += wr;
+      t = wr * ri2;
+    }
+    if (OUT == OUT_POT || OUT == OUT_POTGRAD) lp += pot;
+    if (OUT != OUT_POT) {
+      t += R(3) * md * ri3 * ri2;
+      lx += t * dx - m4.x * ri3;
+      ly += t * dy - m4.y * ri3;
+      lz += t * dz - m4.z * ri3;
+    }
+  }
+}
+
+struct P2PArgs {
+  int p, ps;
+  const int2 *chunks;        // (leaf, first target) per 64-target chunk
+  const int4 *leaf_range;    // level-L ranges
+  const int32_t *leaf_xyz;
+  const int32_t *near_ptr, *near_idx;  // level-L CSR
+  const void *tgt_pos;       // real4 (rx, ry, rz, area) [targets]
+  const void *tgt_nrm;       // real4 [panels] (NGRAD)
+  const void *src_pos;       // real4 (rx, ry, rz, w)
+  const void *src_dip;       // real4 (mx, my, mz, 0)
+  const void *E;             // real [nleaf][4][ps]
+  const int32_t *tperm;      // sorted target -> caller index
+  double sL;
+  const double *xin;
+  double alpha, beta;        // beta already includes 1/(4 pi)
+  int area_scale;
+  int accumulate;
+  double *y;
+  double *dbg_near, *dbg_far;  // sorted order, may be NULL
+};
+
+template <class R, int SRC, int TGT, int OUT>
+__global__ void __launch_bounds__(64) k_p2p(P2PArgs a) {
+  using R4 = typename V4<R>::T;
+  const int2 ch = a.chunks[blockIdx.x];
+  const int leaf = ch.x;
+  const int4 tr = a.leaf_range[leaf];
+  const int tend = (TGT == TGT_PANEL) ? tr.y : tr.w;
+  const int ti = ch.y + threadIdx.x;
+  const bool valid = ti < tend;
+  const R4 *tpos = reinterpret_cast<const R4 *>(a.tgt_pos);
+  const R4 *spos = reinterpret_cast<const R4 *>(a.src_pos);
+  const R4 *sdip = reinterpret_cast<const R4 *>(a.src_dip);
+  R4 tp = valid ? tpos[ti] : tpos[ch.y];
+  const R tx = tp.x, ty = tp.y, tz = tp.z;
+  // ---- far field: L2P from the leaf's evaluation coefficients
+  const R *E = reinterpret_cast<const R *>(a.E) + (size_t)leaf * 4 * a.ps;
+  const R inv_s = R(1.0 / a.sL);
+  R fp = R(0), fgx = R(0), fgy = R(0), fgz = R(0);
+  {
+    const R x = tx * inv_s, y = ty * inv_s, z = tz * inv_s;
+    const int p = a.p;
+    regular_harmonics<R>(p, x, y, z, [&](int n, int m, R re, R im) {
+      const int kr = idx_re(n, m);
+      if (OUT != OUT_NGRAD) {
+        fp += E[kr] * re;
+        if (m > 0) fp += E[idx_im(n, m)] * im;
+      }
+      if (OUT != OUT_POT && n <= p - 2) {
+        fgx += E[a.ps + kr] * re;
+        fgy += E[2 * a.ps + kr] * re;
+        fgz += E[3 * a.ps + kr] * re;
+        if (m > 0) {
+          const int ki = idx_im(n, m);
+          fgx += E[a.ps + ki] * im;
+          fgy += E[2 * a.ps + ki] * im;
+          fgz += E[3 * a.ps + ki] * im;
+        }
+      }
+    });
+  }
+  // ---- near field: direct sum over the near leaves, compensated per leaf
+  R sp = R(0), cp = R(0), sx = R(0), cx = R(0), sy = R(0), cy = R(0), sz = R(0), cz = R(0);
+  int txi, tyi, tzi;
+  xyz_of(a.leaf_xyz[leaf], txi, tyi, tzi);
+  const R sL = (R)a.sL;
+  for (int e = a.near_ptr[leaf]; e < a.near_ptr[leaf + 1]; ++e) {
+    const int sl = a.near_idx[e];
+    const int4 sr = a.leaf_range[sl];
+    const int sb = (SRC == SRC_CHARGE_MONO) ? sr.z : sr.x;
+    const int se = (SRC == SRC_CHARGE_MONO) ? sr.w : sr.y;
+    if (sb == se) continue;
+    int sxi, syi, szi;
+    xyz_of(a.leaf_xyz[sl], sxi, syi, szi);
+    // target relative to the source leaf centre
+    const R ux = tx + R(txi - sxi) * sL, uy = ty + R(tyi - syi) * sL, uz = tz + R(tzi - szi) * sL;
+    R lp = R(0), lx = R(0), ly = R(0), lz = R(0);
+    const bool self = (SRC != SRC_CHARGE_MONO) && (TGT == TGT_PANEL) && (sl == leaf);
+    if (self) {
+      for (int j = sb; j < se; ++j) {
+        R ri;
+        const R4 s4 = spos[j];
+        const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
+        const R r2 = dx * dx + dy * dy + dz * dz;
+        ri = (j == ti) ? R(0) : rsq(r2);  // K'_ii = 0: the self panel is skipped by index
+        pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
+      }
+    } else {
+      for (int j = sb; j < se; ++j) {
+        const R4 s4 = spos[j];
+        const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
+        const R r2 = dx * dx + dy * dy + dz * dz;
+        const R ri = rsq(r2);
+        pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
+      }
+    }
+    // Kahan accumulation of the per-leaf partial sums
+    {
+      R y_ = lp - cp, t_ = sp + y_;
+      cp = (t_ - sp) - y_;
+      sp = t_;
+      y_ = lx - cx; t_ = sx + y_; cx = (t_ - sx) - y_; sx = t_;
+      y_ = ly - cy; t_ = sy + y_; cy = (t_ - sy) - y_; sy = t_;
+      y_ = lz - cz; t_ = sz + y_; cz = (t_ - sz) - y_; sz = t_;
+    }
+  }
+  if (!valid) return;
+  // the near sums hold -grad for monopoles (sum w d / r^3) and the dipole
+  // gradient with the same sign convention: grad = -(sx, sy, sz)
+  const int64_t u = a.tperm[ti];
+  double near_v, far_v;
+  double res[4];
+  int nres = 1;
+  if (OUT == OUT_POT) {
+    near_v = (double)sp;
+    far_v = (double)fp;
+    res[0] = near_v + far_v;
+  } else if (OUT == OUT_NGRAD) {
+    const R4 nn = reinterpret_cast<const R4 *>(a.tgt_nrm)[ti];
+    near_v = -((double)nn.x * sx + (double)nn.y * sy + (double)nn.z * sz);
+    far_v = (double)nn.x * fgx + (double)nn.y * fgy + (double)nn.z * fgz;
+    res[0] = near_v + far_v;
+  } else {
+    near_v = (double)sp;
+    far_v = (double)fp;
+    res[0] = near_v + far_v;
+    res[1] = -(double)sx + (double)fgx;
+    res[2] = -(double)sy + (double)fgy;
+    res[3] = -(double)sz + (double)fgz;
+    nres = 4;
+  }
+  if (a.dbg_near) {
+    a.dbg_near[ti] = near_v;
+    a.dbg_far[ti] = far_v;
+  }
+  double scale = a.beta;
+  if (a.area_scale) scale *= (double)tp.w;
+  if (nres == 1) {
+    double v = scale * res[0];
+    if (a.xin) v += a.alpha * a.xin[u];
+    if (a.accumulate) v += a.y[u];
+    a.y[u] = v;
+  } else {
+    for (int k = 0; k < 4; ++k) {
+      double v = scale * res[k];
+      if (a.accumulate) v += a.y[4 * u + k];
+      a.y[4 * u + k] = v;
+    }
+  }
+}
+
+template <class R>
+void set_rec_constants() {
+  static bool done = false;
+  if (done) return;
+  float r1f[PMAX + 1][PMAX + 1] = {}, r2f[PMAX + 1][PMAX + 1] = {}, hf[PMAX + 1] = {};
+  double r1d[PMAX + 1][PMAX + 1] = {}, r2d[PMAX + 1][PMAX + 1] = {}, hd[PMAX + 1] = {};
+  for (int n = 0; n <= PMAX; ++n)
+    for (int m = 0; m <= PMAX; ++m)
+      if (n > m) {
+        double den = double(n * n - m * m);
+        r1d[n][m] = (2.0 * n - 1.0) / den;
+        r2d[n][m] = 1.0 / den;
+        r1f[n][m] = (float)r1d[n][m];
+        r2f[n][m] = (float)r2d[n][m];
+      }
+  for (int m = 1; m <= PMAX; ++m) {
+    hd[m] = 1.0 / (2.0 * m);
+    hf[m] = (float)hd[m];
+  }
+  HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(c_rec1_f), r1f, sizeof(r1f)));
+  HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(c_rec2_f), r2f, sizeof(r2f)));
+  HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(c_rec1_d), r1d, sizeof(r1d)));
+  HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(c_rec2_d), r2d, sizeof(r2d)));
+  HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(c_half_inv_m_f), hf, sizeof(hf)));
+  HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(c_half_inv_m_d), hd, sizeof(hd)));
+  done = true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- driver
+
+void prof_begin(Tree &T, int stage, hipStream_t s) {
+  if (!T.prof) return;
+  HIP_OK(hipEventRecord(T.ev[2 * stage], s));
+}
+
+void prof_end(Tree &T, int stage, hipStream_t s) {
+  if (!T.prof) return;
+  HIP_OK(hipEventRecord(T.ev[2 * stage + 1], s));
+  HIP_OK(hipEventSynchronize(T.ev[2 * stage + 1]));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, T.ev[2 * stage], T.ev[2 * stage + 1]));
+  T.prof_ms[stage] += ms;
+  T.prof_cnt[stage] += 1;
+}
+
+static PrecBufs &bufs(Tree &T, int prec, hipStream_t s) {
+  PrecBufs *&pb = (prec == BEMFMM_FP64) ? T.pb64 : T.pb32;
+  if (!pb) {
+    pb = new PrecBufs();
+    const size_t rs = (prec == BEMFMM_FP64) ? 8 : 4;
+    const int64_t npts = std::max<int64_t>(std::max(T.N, T.Q), 1);
+    pb->src_pos.alloc(npts * 4 * rs);
+    pb->src_dip.alloc(npts * 4 * rs);
+    pb->M.alloc((size_t)T.ncell_tot * T.ps * rs);
+    pb->L.alloc((size_t)T.ncell_tot * T.ps * rs);
+    pb->m2l_out.alloc((size_t)std::max<int64_t>(T.nfar, 1) * T.ps * rs);
+    pb->E.alloc((size_t)T.ncell[T.L] * 4 * T.ps * rs);
+    pb->dbg_near.alloc(npts);
+    pb->dbg_far.alloc(npts);
+    pb->M.zero(s);
+    pb->L.zero(s);
+    pb->E.zero(s);
+    pb->src_dip.zero(s);
+    pb->prec = prec;
+  }
+  return *pb;
+}
+
+template <class R>
+static void launch_p2m(Tree &T, PrecBufs &B, int src, hipStream_t s) {
+  using R4 = typename V4<R>::T;
+  const int L = T.L, ps = T.ps;
+  const int64_t CL = T.ncell[L];
+  const double sL = T.side / double(1 << L);
+  const size_t shm = (size_t)64 * (ps + 1) * sizeof(R);
+  const R4 *spos = reinterpret_cast<const R4 *>(B.src_pos.p);
+  const R4 *sdip = reinterpret_cast<const R4 *>(B.src_dip.p);
+  R *M = reinterpret_cast<R *>(B.M.p) + (size_t)T.coff[L] * ps;
+  const int4 *rg = T.crange.p + T.coff[L];
+  const R inv = R(1.0 / sL);
+  switch (src) {
+    case SRC_PANEL_MONO:
+      k_p2m<R, true, false><<<CL, 64, shm, s>>>(T.p, ps, CL, rg, 0, spos, sdip, inv, M);
+      break;
+    case SRC_CHARGE_MONO:
+      k_p2m<R, true, false><<<CL, 64, shm, s>>>(T.p, ps, CL, rg, 1, spos, sdip, inv, M);
+      break;
+    case SRC_PANEL_DIP:
+      k_p2m<R, false, true><<<CL, 64, shm, s>>>(T.p, ps, CL, rg, 0, spos, sdip, inv, M);
+      break;
+    default:
+      k_p2m<R, true, true><<<CL, 64, shm, s>>>(T.p, ps, CL, rg, 0, spos, sdip, inv, M);
+      break;
+  }
+  LAUNCH_OK();
+}
+
+template <class R>
+static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
+  using R4 = typename V4<R>::T;
+  set_rec_constants<R>();
+  const bool f64 = std::is_same<R, double>::value;
+  const int L = T.L, p = T.p, ps = T.ps;
+  const int TB = 256;
+  const double sL = T.side / double(1 << L);
+  const bool src_charges = rq.src == SRC_CHARGE_MONO;
+  R4 *spos = reinterpret_cast<R4 *>(B.src_pos.p);
+  R4 *sdip = reinterpret_cast<R4 *>(B.src_dip.p);
+  R *M = reinterpret_cast<R *>(B.M.p);
+  R *Lx = reinterpret_cast<R *>(B.L.p);
+  R *m2l = reinterpret_cast<R *>(B.m2l_out.p);
+  R *E = reinterpret_cast<R *>(B.E.p);
+
+  prof_begin(T, ST_OTHER, s);
+  if (src_charges) {
+    if (T.Q > 0) {
+      k_pack_charges<R><<<cdiv(T.Q, TB), TB, 0, s>>>(
+          T.Q, T.qperm.p, reinterpret_cast<const R4 *>(f64 ? (void *)T.q64pos.p : (void *)T.q32pos.p), rq.wmono, spos);
+      LAUNCH_OK();
+    }
+  } else {
+    k_pack_panels<R><<<cdiv(T.N, TB), TB, 0, s>>>(
+        T.N, T.pperm.p, reinterpret_cast<const R4 *>(f64 ? (void *)T.p64pos.p : (void *)T.p32pos.p),
+        reinterpret_cast<const R4 *>(f64 ? (void *)T.p64nrm.p : (void *)T.p32nrm.p), T.area.p, rq.wmono,
+        rq.mono_area ? 1 : 0, rq.wdip, spos, sdip);
+    LAUNCH_OK();
+  }
+  prof_end(T, ST_OTHER, s);
+
+  const bool far = (L >= 2) && T.nfar > 0;
+  if (far) {
+    prof_begin(T, ST_P2M, s);
+    launch_p2m<R>(T, B, rq.src, s);
+    prof_end(T, ST_P2M, s);
+    // M2M, levels L-1 .. 2
+    prof_begin(T, ST_M2M, s);
+    const R *Sm = f64 ? reinterpret_cast<const R *>(T.t_m2m64.p) : reinterpret_cast<const R *>(T.t_m2m32.p);
+    for (int l = L - 1; l >= 2; --l) {
+      k_m2m<R><<<T.ncell[l], 64, 0, s>>>(p * p, ps, T.coff[l], T.ncell[l], T.cchild.p, T.ckey.p, Sm, M);
+      LAUNCH_OK();
+    }
+    prof_end(T, ST_M2M, s);
+    // M2L, every level in one launch
+    prof_begin(T, ST_M2L, s);
+    const int NT = ps / 16;
+    if (T.n_m2l_tiles > 0) {
+      const dim3 grid((unsigned)T.n_m2l_tiles);
+#define M2L_CASE(nt)                                                                                           \
+  case nt:                                                                                                     \
+    if (f64)                                                                                                   \
+      k_m2l_f64<nt><<<grid, 256, 0, s>>>(T.m2l_tile_group.p, T.m2l_tile_row.p, T.m2l_group_off.p,              \
+                                         T.m2l_group_end.p, T.far_order.p, T.far_ts.p, T.t_m2l64.p,           \
+                                         reinterpret_cast<const double *>(M), reinterpret_cast<double *>(m2l)); \
+    else                                                                                                       \
+      k_m2l_f32<nt><<<grid, 256, 0, s>>>(T.m2l_tile_group.p, T.m2l_tile_row.p, T.m2l_group_off.p,              \
+                                         T.m2l_group_end.p, T.far_order.p, T.far_ts.p, T.t_m2l32.p,           \
+                                         reinterpret_cast<const float *>(M), reinterpret_cast<float *>(m2l));  \
+    break;
+      switch (NT) {
+        M2L_CASE(1)
+        M2L_CASE(2)
+        M2L_CASE(3)
+        M2L_CASE(4)
+        M2L_CASE(5)
+        M2L_CASE(6)
+        M2L_CASE(7)
+        M2L_CASE(8)
+        M2L_CASE(9)
+        default:
+          BF_THROW(BEMFMM_EINVAL, "unsupported expansion order");
+      }
+#undef M2L_CASE
+      LAUNCH_OK();
+    }
+    prof_end(T, ST_M2L, s);
+    // downward pass, levels 2 .. L
+    prof_begin(T, ST_L2L, s);
+    const R *Sl = f64 ? reinterpret_cast<const R *>(T.t_l2l64.p) : reinterpret_cast<const R *>(T.t_l2l32.p);
+    for (int l = 2; l <= L; ++l) {
+      const bool leaf = (l == L);
+      const size_t shm2 = (size_t)ps * sizeof(R);
+      k_downward<R><<<T.ncell[l], 64, shm2, s>>>(p, ps, T.coff[l], T.ncell[l], l > 2 ? 1 : 0, T.cparent.p, T.ckey.p,
+                                                 Sl, T.far_ptr.p, m2l, Lx, leaf ? 1 : 0, R(1.0 / sL), E);
+      LAUNCH_OK();
+    }
+    prof_end(T, ST_L2L, s);
+  } else {
+    B.E.zero(s);
+  }
+
+  // P2P + L2P + the operator's combination
+  prof_begin(T, ST_P2P, s);
+  P2PArgs a{};
+  a.p = p;
+  a.ps = ps;
+  const bool tgt_ch = rq.tgt == TGT_CHARGE;
+  a.chunks = tgt_ch ? T.chunk_q.p : T.chunk_p.p;
+  const int64_t nchunks = tgt_ch ? T.nchunk_q : T.nchunk_p;
+  a.leaf_range = T.crange.p + T.coff[L];
+  a.leaf_xyz = T.cxyz.p + T.coff[L];
+  a.near_ptr = T.near_ptr.p + T.near_ptr_off[L];
+  a.near_idx = T.near_idx.p + T.near_off[L];
+  a.tgt_pos = tgt_ch ? (f64 ? (const void *)T.q64pos.p : (const void *)T.q32pos.p)
+                     : (f64 ? (const void *)T.p64pos.p : (const void *)T.p32pos.p);
+  a.tgt_nrm = f64 ? (const void *)T.p64nrm.p : (const void *)T.p32nrm.p;
+  a.src_pos = spos;
+  a.src_dip = sdip;
+  a.E = E;
+  a.tperm = tgt_ch ? T.qperm.p : T.pperm.p;
+  a.sL = sL;
+  a.xin = rq.xin;
+  a.alpha = rq.alpha;
+  a.beta = rq.beta / (4.0 * PI);
+  a.area_scale = rq.area_scale ? 1 : 0;
+  a.accumulate = rq.accumulate ? 1 : 0;
+  a.y = rq.y;
+  a.dbg_near = B.dbg_near.p;
+  a.dbg_far = B.dbg_far.p;
+  B.last_tgt = rq.tgt;
+  if (nchunks > 0) {
+#define P2P_CALL(S, Tg, O) k_p2p<R, S, Tg, O><<<nchunks, 64, 0, s>>>(a)
+    if (!tgt_ch) {
+      if (rq.src == SRC_PANEL_MONO && rq.out == OUT_NGRAD) P2P_CALL(SRC_PANEL_MONO, TGT_PANEL, OUT_NGRAD);
+      else if (rq.src == SRC_PANEL_DIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_DIP, TGT_PANEL, OUT_POT);
+      else if (rq.src == SRC_CHARGE_MONO && rq.out == OUT_NGRAD) P2P_CALL(SRC_CHARGE_MONO, TGT_PANEL, OUT_NGRAD);
+      else if (rq.src == SRC_CHARGE_MONO && rq.out == OUT_POT) P2P_CALL(SRC_CHARGE_MONO, TGT_PANEL, OUT_POT);
+      else BF_THROW(BEMFMM_EINVAL, "unsupported FMM request (panel targets)");
+    } else {
+      if (rq.src == SRC_PANEL_MONO && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_MONO, TGT_CHARGE, OUT_POT);
+      else if (rq.src == SRC_PANEL_DIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_DIP, TGT_CHARGE, OUT_POT);
+      else if (rq.src == SRC_PANEL_MONODIP && rq.out == OUT_POTGRAD) P2P_CALL(SRC_PANEL_MONODIP, TGT_CHARGE, OUT_POTGRAD);
+      else if (rq.src == SRC_PANEL_MONODIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_MONODIP, TGT_CHARGE, OUT_POT);
+      else BF_THROW(BEMFMM_EINVAL, "unsupported FMM request (charge targets)");
+    }
+#undef P2P_CALL
+    LAUNCH_OK();
+  }
+  prof_end(T, ST_P2P, s);
+  B.have = true;
+}
+
+void fmm_apply(Tree &T, int precision, const FmmRequest &rq, hipStream_t s) {
+  const int prec = (precision == BEMFMM_FP64) ? BEMFMM_FP64 : BEMFMM_FP32;
+  if (rq.tgt == TGT_CHARGE && T.Q == 0) return;
+  PrecBufs &B = bufs(T, prec, s);
+  if (T.prof && !T.ev_init) {
+    for (auto &e : T.ev) HIP_OK(hipEventCreate(&e));
+    T.ev_init = true;
+  }
+  if (prec == BEMFMM_FP64)
+    run_fmm<double>(T, B, rq, s);
+  else
+    run_fmm<float>(T, B, rq, s);
+}
+
+void fmm_free(Tree &T) {
+  delete T.pb32;
+  delete T.pb64;
+  T.pb32 = T.pb64 = nullptr;
+}
+
+void debug_expansions(Tree &T, int precision, int which, double *out_host, hipStream_t s) {
+  PrecBufs *B = (precision == BEMFMM_FP64) ? T.pb64 : T.pb32;
+  if (!B || !B->have) BF_THROW(BEMFMM_ESTATE, "no matvec has run at this precision");
+  const size_t n = (size_t)T.ncell_tot * T.ps;
+  const int np2 = T.p * T.p;
+  std::vector<double> full(n);
+  const DBuf<char> &src = which ? B->L : B->M;
+  if (B->prec == BEMFMM_FP64) {
+    HIP_OK(hipMemcpyAsync(full.data(), src.p, n * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  } else {
+    std::vector<float> f(n);
+    HIP_OK(hipMemcpyAsync(f.data(), src.p, n * 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (size_t i = 0; i < n; ++i) full[i] = f[i];
+  }
+  for (int64_t c = 0; c < T.ncell_tot; ++c)
+    for (int k = 0; k < np2; ++k) out_host[(size_t)c * np2 + k] = full[(size_t)c * T.ps + k];
+}
+
+void debug_fields(Tree &T, int precision, double *near_host, double *far_host, hipStream_t s) {
+  PrecBufs *B = (precision == BEMFMM_FP64) ? T.pb64 : T.pb32;
+  if (!B || !B->have) BF_THROW(BEMFMM_ESTATE, "no matvec has run at this precision");
+  const int64_t nt = (B->last_tgt == TGT_CHARGE) ? T.Q : T.N;
+  std::vector<double> ns(nt), fs(nt);
+  std::vector<int32_t> perm(nt);
+  HIP_OK(hipMemcpyAsync(ns.data(), B->dbg_near.p, nt * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(fs.data(), B->dbg_far.p, nt * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(perm.data(), (B->last_tgt == TGT_CHARGE) ? T.qperm.p : T.pperm.p, nt * 4,
+                        hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const double k4 = 1.0 / (4.0 * PI);
+  for (int64_t i = 0; i < nt; ++i) {
+    if (near_host) near_host[perm[i]] = ns[i] * k4;
+    if (far_host) far_host[perm[i]] = fs[i] * k4;
+  }
+}
+
+}  // namespace bemfmm

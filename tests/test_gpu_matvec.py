@@ -1,0 +1,169 @@
+"""GPU FMM products vs the FP64 dense oracle (Section 2.1 operators, Section
+2.3 fast summation), element by element, plus stage-level checks of the
+expansions against their definitions."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import harmonics as H
+from oracle import tree as OT
+
+from gpu_common import requires_gpu, lib, dev, host, rel_l2
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+EPS_IN, EPS_OUT = 4.0, 80.0
+F = 1.0 - EPS_IN / EPS_OUT
+
+
+def dense_ops(p, g, x, qv, y):
+    """Oracle results of the six operators."""
+    return {
+        0: oracle.apply_A(g, F, x),
+        1: oracle.apply_AT(g, F, y),
+        2: oracle.field_B(g, p.charge_pos, qv),
+        3: oracle.apply_BT(g, p.charge_pos, y),
+        4: oracle.apply_C(g, p.charge_pos, x),
+        5: oracle.apply_CT(g, p.charge_pos, qv),
+    }
+
+
+def _inputs(p, seed=7):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=p.n_panels)
+    y = rng.normal(size=p.n_panels)
+    qv = rng.normal(size=p.n_charges)
+    return x, y, qv
+
+
+def _run_all(B, t, x, y, qv, prec):
+    ins = {0: x, 1: y, 2: qv, 3: y, 4: x, 5: qv}
+    return {op: host(B.fmm_matvec(t, op, prec, dev(ins[op]))) for op in range(6)}
+
+
+@pytest.mark.parametrize("prec,tol_direct", [(0, 1e-12), (1, 2e-6)])
+def test_direct_limit_matches_dense(prec, tol_direct):
+    """A tree with one level (ncrit huge) has no far field: the FMM is the
+    direct sum, so FP64 must equal the dense oracle to rounding."""
+    B = lib()
+    p = synth.kirkwood(3, n_charges=30)
+    g = oracle.geometry(p.verts, p.tris)
+    x, y, qv = _inputs(p)
+    t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params(ncrit=100000))
+    assert t.info["n_far_pairs"] == 0
+    got = _run_all(B, t, x, y, qv, prec)
+    want = dense_ops(p, g, x, qv, y)
+    for op in range(6):
+        print(f"[direct] prec={prec} op={op} err={rel_l2(got[op], want[op]):.3e}", flush=True)
+        assert rel_l2(got[op], want[op]) <= tol_direct, op
+
+
+CASES = [
+    ("born-L3", lambda: synth.born(3), 32),
+    ("kirkwood-L4-20q", lambda: synth.kirkwood(4, n_charges=20), 32),
+    ("blobby-L5", lambda: synth.blobby(5), 32),
+]
+
+
+@pytest.mark.parametrize("name,make,ncrit", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fmm_operators_match_dense(name, make, ncrit, prec):
+    """Every operator at p = 10, theta = 0.5: relative L2 error <= 1e-5."""
+    B = lib()
+    p = make()
+    g = oracle.geometry(p.verts, p.tris)
+    x, y, qv = _inputs(p)
+    t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params(ncrit=ncrit))
+    print(f"[fmm] {name} prec={prec} L={t.info['leaf_level']} far={t.info['n_far_pairs']}", flush=True)
+    got = _run_all(B, t, x, y, qv, prec)
+    want = dense_ops(p, g, x, qv, y)
+    for op in range(6):
+        e = rel_l2(got[op], want[op])
+        print(f"    op={op} rel_l2={e:.3e}", flush=True)
+        assert e <= 1e-5, (op, e)
+
+
+def test_fmm_deterministic():
+    B = lib()
+    p = synth.blobby(4)
+    x, _, _ = _inputs(p)
+    t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params(ncrit=16))
+    a = host(B.fmm_matvec(t, 0, 1, dev(x)))
+    b = host(B.fmm_matvec(t, 0, 1, dev(x)))
+    np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 2e-6)])
+def test_expansions_match_definitions(prec, tol):
+    """Multipole expansions of every cell (P2M at the leaves, M2M above)
+    equal the definition M_n^m = sum w conj(R_n^m(y - X)) applied directly
+    to the cell's sources (M2M is exact), element by element."""
+    B = lib()
+    p = synth.blobby(4)
+    g = oracle.geometry(p.verts, p.tris)
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=p.n_panels)
+    t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params(ncrit=16))
+    B.fmm_matvec(t, 0, prec, dev(x))
+    Mg = B.debug_expansions(t, prec, 0)
+    ex = B.tree_export(t)
+    lo, side = np.array(ex["info"]["lo"]), ex["info"]["side"]
+    lev = ex["cell_level"]
+    w = g.a * x
+    perm = ex["panel_perm"]
+    L = ex["info"]["leaf_level"]
+    checked = 0
+    for l in range(2, L + 1):
+        sel = np.nonzero(lev == l)[0]
+        s = side / (1 << l)
+        for c in sel[:: max(1, len(sel) // 12)]:
+            k = OT.deinterleave(np.array([ex["cell_key"][c]], dtype=np.int64), l)[0]
+            X = lo + (k + 0.5) * s
+            b, e = ex["cell_range"][c][:2]
+            if e == b:
+                continue
+            idx = perm[b:e]
+            want = H.p2m(g.c[idx], w[idx], X, s, 10)
+            scale = np.abs(want).max()
+            err = np.abs(Mg[c] - want).max() / scale
+            assert err <= tol, (l, c, err)
+            checked += 1
+    assert checked > 10
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_near_and_far_fields(prec):
+    """P2P near field equals the direct sum over the near leaves (to
+    rounding); the L2P far field equals the exact sum over all other sources
+    to within the truncation error."""
+    B = lib()
+    p = synth.blobby(4)
+    g = oracle.geometry(p.verts, p.tris)
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=p.n_panels)
+    t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params(ncrit=16))
+    B.fmm_matvec(t, 0, prec, dev(x))
+    near, far = B.debug_fields(t, prec, p.n_panels)
+    ex = B.tree_export(t)
+    perm = ex["panel_perm"]
+    L = ex["info"]["leaf_level"]
+    lev = ex["cell_level"]
+    leaf_rng = ex["cell_range"][lev == L]
+    ptr, idx = ex["near_ptr"], ex["near_idx"]
+    leaf_of = np.zeros(p.n_panels, dtype=np.int64)
+    for li, (b, e, _, _) in enumerate(leaf_rng):
+        leaf_of[perm[b:e]] = li
+    w = g.a * x
+    Kall = oracle.apply_Kp(g, x)
+    tgts = rng.choice(p.n_panels, size=40, replace=False)
+    for i in tgts:
+        li = leaf_of[i]
+        srcs = np.concatenate([perm[leaf_rng[s][0]:leaf_rng[s][1]] for s in idx[ptr[li]:ptr[li + 1]]])
+        srcs = srcs[srcs != i]
+        d = g.c[i] - g.c[srcs]
+        r = np.linalg.norm(d, axis=1)
+        want_near = -np.sum(w[srcs] * (d @ g.n[i]) / r ** 3) / (4 * np.pi)
+        want_far = Kall[i] - want_near
+        tol_n = 1e-12 if prec == 0 else 2e-6
+        assert abs(near[i] - want_near) <= tol_n * np.abs(Kall).max(), i
+        assert abs(far[i] - want_far) <= 1e-6 * np.abs(Kall).max(), i
