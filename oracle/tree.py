@@ -15,8 +15,12 @@ is silent:
 * Keys: 10 bits per axis, k_d = clamp(floor((x_d - lo_d) * (1024 / side)), 0, 1023),
   interleaved as bit 3b+2 = x bit b, 3b+1 = y bit b, 3b = z bit b (30-bit key).
 * Order: points stably sorted by key (ties keep input order).
-* Leaf level L: the smallest level (0..10) whose mean number of panels per
-  non-empty panel cell is <= ncrit; 10 if none.  Uniform-depth sparse tree:
+* Leaf level L: with m_l = N / (number of non-empty panel cells at level l),
+  let l* be the smallest level (0..10) with m_l <= ncrit (10 if none); L is
+  l* - 1 if m_{l*-1} is closer to ncrit on a log scale (m_{l*-1} m_{l*} <
+  ncrit^2, compared exactly as N^2 < ncrit^2 c_{l*-1} c_{l*}), else l*.
+  On a surface the occupancy drops about 4x per level, so this keeps the
+  mean leaf occupancy within a factor of 2 of ncrit.  Uniform-depth sparse tree:
   cells at level l are the distinct level-l prefixes (key >> 3(10-l)) of
   panels and charges together, in increasing order.
 * MAC between two same-level cells with integer offset o (source minus
@@ -112,10 +116,12 @@ class Tree:
 
 
 def choose_level(panel_key: np.ndarray, ncrit: int) -> int:
-    N = panel_key.shape[0]
+    N = int(panel_key.shape[0])
+    counts = [int(np.unique(panel_key >> (3 * (LMAX - l))).shape[0]) for l in range(LMAX + 1)]
     for l in range(0, LMAX + 1):
-        ncell = np.unique(panel_key >> (3 * (LMAX - l))).shape[0]
-        if N <= ncrit * ncell:  # mean occupancy N / ncell <= ncrit
+        if N <= ncrit * counts[l]:  # mean occupancy N / c_l <= ncrit
+            if l > 0 and N * N < ncrit * ncrit * counts[l - 1] * counts[l]:
+                return l - 1
             return l
     return LMAX
 

@@ -168,15 +168,17 @@ struct Tree {
   int64_t n_m2l_tiles = 0, n_m2l_groups = 0;
   int64_t p2p_pairs_pp = 0;
 
-  // translation tables on the device (FP32 MFMA-swizzled M2L; FP64 too)
+  // translation tables on the device, shared by every tree with the same
+  // (device, p, MAC) and kept until the process ends
   const Tables *tab = nullptr;
-  DBuf<float> t_m2l32;   // [noff][PS/4 kk][PS/16 ct][64 lanes]
-  DBuf<double> t_m2l64;  // same layout
-  DBuf<float> t_m2m32, t_l2l32;   // [8][ps in][ps out] (transposed: lanes read rows)
-  DBuf<double> t_m2m64, t_l2l64;
+  const float *t_m2l32 = nullptr;   // [noff][PS/4 kk][PS/16 ct][64 lanes], MFMA B-operand order
+  const double *t_m2l64 = nullptr;  // same layout
+  const float *t_m2m32 = nullptr, *t_l2l32 = nullptr;   // [8][ps in][ps out] (transposed)
+  const double *t_m2m64 = nullptr, *t_l2l64 = nullptr;
 
-  // P2P work decomposition: (leaf, first sorted index) per 64-target chunk
-  DBuf<int2> chunk_p, chunk_q;
+  // P2P work decomposition: (leaf, first sorted index, count, lane groups)
+  // per chunk of at most 64 targets of one leaf
+  DBuf<int4> chunk_p, chunk_q;
   int64_t nchunk_p = 0, nchunk_q = 0;
 
   PrecBufs *pb32 = nullptr, *pb64 = nullptr;

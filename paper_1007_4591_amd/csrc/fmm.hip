@@ -510,7 +510,7 @@ __device__ __forceinline__ void pair_accumulate(const typename V4<R>::T &s4, con
 
 struct P2PArgs {
   int p, ps;
-  const int2 *chunks;        // (leaf, first target) per 64-target chunk
+  const int4 *chunks;        // (leaf, first target, count, lane groups) per chunk
   const int4 *leaf_range;    // level-L ranges
   const int32_t *leaf_xyz;
   const int32_t *near_ptr, *near_idx;  // level-L CSR
@@ -529,20 +529,101 @@ struct P2PArgs {
   double *dbg_near, *dbg_far;  // sorted order, may be NULL
 };
 
+// One wave per chunk of up to 64 targets of one leaf.  A chunk of n targets
+// uses G = 64 / n lane groups: lane l works on target l % n and on every
+// G-th source of each near leaf (starting at l / n), so small leaves still
+// fill the wave.  Each lane sums one source leaf in plain arithmetic, adds
+// the leaf total to a compensated (Kahan) accumulator, and the G partial
+// results are added in group order through LDS.  The far field (L2P from
+// the leaf's evaluation coefficients) and the operator's combination are
+// applied once per target.
 template <class R, int SRC, int TGT, int OUT>
 __global__ void __launch_bounds__(64) k_p2p(P2PArgs a) {
   using R4 = typename V4<R>::T;
-  const int2 ch = a.chunks[blockIdx.x];
-  const int leaf = ch.x;
-  const int4 tr = a.leaf_range[leaf];
-  const int tend = (TGT == TGT_PANEL) ? tr.y : tr.w;
-  const int ti = ch.y + threadIdx.x;
-  const bool valid = ti < tend;
+  __shared__ R red[4][64];
+  const int4 ch = a.chunks[blockIdx.x];  // (leaf, first target, count, groups)
+  const int leaf = ch.x, count = ch.z, G = ch.w;
+  const int lane = threadIdx.x;
+  const int g = lane / count, tl = lane - g * count;
+  const bool active = g < G;
+  const int ti = ch.y + tl;
   const R4 *tpos = reinterpret_cast<const R4 *>(a.tgt_pos);
   const R4 *spos = reinterpret_cast<const R4 *>(a.src_pos);
   const R4 *sdip = reinterpret_cast<const R4 *>(a.src_dip);
-  R4 tp = valid ? tpos[ti] : tpos[ch.y];
+  const R4 tp = tpos[ti];
   const R tx = tp.x, ty = tp.y, tz = tp.z;
+  // ---- near field: direct sum over the near leaves, compensated per leaf
+  R sp = R(0), cp = R(0), sx = R(0), cx = R(0), sy = R(0), cy = R(0), sz = R(0), cz = R(0);
+  int txi, tyi, tzi;
+  xyz_of(a.leaf_xyz[leaf], txi, tyi, tzi);
+  const R sL = (R)a.sL;
+  const int e0 = a.near_ptr[leaf], e1 = a.near_ptr[leaf + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int sl = a.near_idx[e];
+    const int4 sr = a.leaf_range[sl];
+    const int sb = (SRC == SRC_CHARGE_MONO) ? sr.z : sr.x;
+    const int se = (SRC == SRC_CHARGE_MONO) ? sr.w : sr.y;
+    if (sb == se) continue;
+    int sxi, syi, szi;
+    xyz_of(a.leaf_xyz[sl], sxi, syi, szi);
+    // target relative to the source leaf centre
+    const R ux = tx + R(txi - sxi) * sL, uy = ty + R(tyi - syi) * sL, uz = tz + R(tzi - szi) * sL;
+    R lp = R(0), lx = R(0), ly = R(0), lz = R(0);
+    const bool self = (SRC != SRC_CHARGE_MONO) && (TGT == TGT_PANEL) && (sl == leaf);
+    if (active) {
+      if (self) {
+        for (int j = sb + g; j < se; j += G) {
+          const R4 s4 = spos[j];
+          const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
+          const R r2 = dx * dx + dy * dy + dz * dz;
+          const R ri = (j == ti) ? R(0) : rsq(r2);  // K'_ii = 0: the self panel is skipped by index
+          pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
+        }
+      } else {
+#pragma unroll 4
+        for (int j = sb + g; j < se; j += G) {
+          const R4 s4 = spos[j];
+          const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
+          const R r2 = dx * dx + dy * dy + dz * dz;
+          const R ri = rsq(r2);
+          pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
+        }
+      }
+    }
+    // Kahan accumulation of the per-leaf partial sums
+    {
+      R y_ = lp - cp, t_ = sp + y_;
+      cp = (t_ - sp) - y_;
+      sp = t_;
+      y_ = lx - cx; t_ = sx + y_; cx = (t_ - sx) - y_; sx = t_;
+      y_ = ly - cy; t_ = sy + y_; cy = (t_ - sy) - y_; sy = t_;
+      y_ = lz - cz; t_ = sz + y_; cz = (t_ - sz) - y_; sz = t_;
+    }
+  }
+  // ---- combine the G lane groups in group order
+  if (G > 1) {
+    red[0][lane] = sp;
+    red[1][lane] = sx;
+    red[2][lane] = sy;
+    red[3][lane] = sz;
+    __syncthreads();
+    if (g == 0) {
+      R s0 = red[0][tl], c0 = R(0), s1 = red[1][tl], c1 = R(0), s2 = red[2][tl], c2 = R(0), s3 = red[3][tl],
+        c3 = R(0);
+      for (int h = 1; h < G; ++h) {
+        const int k = h * count + tl;
+        R y_ = red[0][k] - c0, t_ = s0 + y_; c0 = (t_ - s0) - y_; s0 = t_;
+        y_ = red[1][k] - c1; t_ = s1 + y_; c1 = (t_ - s1) - y_; s1 = t_;
+        y_ = red[2][k] - c2; t_ = s2 + y_; c2 = (t_ - s2) - y_; s2 = t_;
+        y_ = red[3][k] - c3; t_ = s3 + y_; c3 = (t_ - s3) - y_; s3 = t_;
+      }
+      sp = s0;
+      sx = s1;
+      sy = s2;
+      sz = s3;
+    }
+  }
+  if (g != 0) return;
   // ---- far field: L2P from the leaf's evaluation coefficients
   const R *E = reinterpret_cast<const R *>(a.E) + (size_t)leaf * 4 * a.ps;
   const R inv_s = R(1.0 / a.sL);
@@ -569,54 +650,8 @@ __global__ void __launch_bounds__(64) k_p2p(P2PArgs a) {
       }
     });
   }
-  // ---- near field: direct sum over the near leaves, compensated per leaf
-  R sp = R(0), cp = R(0), sx = R(0), cx = R(0), sy = R(0), cy = R(0), sz = R(0), cz = R(0);
-  int txi, tyi, tzi;
-  xyz_of(a.leaf_xyz[leaf], txi, tyi, tzi);
-  const R sL = (R)a.sL;
-  for (int e = a.near_ptr[leaf]; e < a.near_ptr[leaf + 1]; ++e) {
-    const int sl = a.near_idx[e];
-    const int4 sr = a.leaf_range[sl];
-    const int sb = (SRC == SRC_CHARGE_MONO) ? sr.z : sr.x;
-    const int se = (SRC == SRC_CHARGE_MONO) ? sr.w : sr.y;
-    if (sb == se) continue;
-    int sxi, syi, szi;
-    xyz_of(a.leaf_xyz[sl], sxi, syi, szi);
-    // target relative to the source leaf centre
-    const R ux = tx + R(txi - sxi) * sL, uy = ty + R(tyi - syi) * sL, uz = tz + R(tzi - szi) * sL;
-    R lp = R(0), lx = R(0), ly = R(0), lz = R(0);
-    const bool self = (SRC != SRC_CHARGE_MONO) && (TGT == TGT_PANEL) && (sl == leaf);
-    if (self) {
-      for (int j = sb; j < se; ++j) {
-        R ri;
-        const R4 s4 = spos[j];
-        const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
-        const R r2 = dx * dx + dy * dy + dz * dz;
-        ri = (j == ti) ? R(0) : rsq(r2);  // K'_ii = 0: the self panel is skipped by index
-        pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
-      }
-    } else {
-      for (int j = sb; j < se; ++j) {
-        const R4 s4 = spos[j];
-        const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
-        const R r2 = dx * dx + dy * dy + dz * dz;
-        const R ri = rsq(r2);
-        pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
-      }
-    }
-    // Kahan accumulation of the per-leaf partial sums
-    {
-      R y_ = lp - cp, t_ = sp + y_;
-      cp = (t_ - sp) - y_;
-      sp = t_;
-      y_ = lx - cx; t_ = sx + y_; cx = (t_ - sx) - y_; sx = t_;
-      y_ = ly - cy; t_ = sy + y_; cy = (t_ - sy) - y_; sy = t_;
-      y_ = lz - cz; t_ = sz + y_; cz = (t_ - sz) - y_; sz = t_;
-    }
-  }
-  if (!valid) return;
-  // the near sums hold -grad for monopoles (sum w d / r^3) and the dipole
-  // gradient with the same sign convention: grad = -(sx, sy, sz)
+  // the near sums hold -grad (sum w d / r^3 for monopoles, and the dipole
+  // terms with the same sign): grad = -(sx, sy, sz)
   const int64_t u = a.tperm[ti];
   double near_v, far_v;
   double res[4];
@@ -797,7 +832,7 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     prof_end(T, ST_P2M, s);
     // M2M, levels L-1 .. 2
     prof_begin(T, ST_M2M, s);
-    const R *Sm = f64 ? reinterpret_cast<const R *>(T.t_m2m64.p) : reinterpret_cast<const R *>(T.t_m2m32.p);
+    const R *Sm = f64 ? reinterpret_cast<const R *>(T.t_m2m64) : reinterpret_cast<const R *>(T.t_m2m32);
     for (int l = L - 1; l >= 2; --l) {
       k_m2m<R><<<T.ncell[l], 64, 0, s>>>(p * p, ps, T.coff[l], T.ncell[l], T.cchild.p, T.ckey.p, Sm, M);
       LAUNCH_OK();
@@ -812,11 +847,11 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   case nt:                                                                                                     \
     if (f64)                                                                                                   \
       k_m2l_f64<nt><<<grid, 256, 0, s>>>(T.m2l_tile_group.p, T.m2l_tile_row.p, T.m2l_group_off.p,              \
-                                         T.m2l_group_end.p, T.far_order.p, T.far_ts.p, T.t_m2l64.p,           \
+                                         T.m2l_group_end.p, T.far_order.p, T.far_ts.p, T.t_m2l64,           \
                                          reinterpret_cast<const double *>(M), reinterpret_cast<double *>(m2l)); \
     else                                                                                                       \
       k_m2l_f32<nt><<<grid, 256, 0, s>>>(T.m2l_tile_group.p, T.m2l_tile_row.p, T.m2l_group_off.p,              \
-                                         T.m2l_group_end.p, T.far_order.p, T.far_ts.p, T.t_m2l32.p,           \
+                                         T.m2l_group_end.p, T.far_order.p, T.far_ts.p, T.t_m2l32,           \
                                          reinterpret_cast<const float *>(M), reinterpret_cast<float *>(m2l));  \
     break;
       switch (NT) {
@@ -838,7 +873,7 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     prof_end(T, ST_M2L, s);
     // downward pass, levels 2 .. L
     prof_begin(T, ST_L2L, s);
-    const R *Sl = f64 ? reinterpret_cast<const R *>(T.t_l2l64.p) : reinterpret_cast<const R *>(T.t_l2l32.p);
+    const R *Sl = f64 ? reinterpret_cast<const R *>(T.t_l2l64) : reinterpret_cast<const R *>(T.t_l2l32);
     for (int l = 2; l <= L; ++l) {
       const bool leaf = (l == L);
       const size_t shm2 = (size_t)ps * sizeof(R);

@@ -11,6 +11,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "common.h"
 
@@ -613,53 +616,80 @@ int read_err(DBuf<int> &e, hipStream_t s) {
 
 }  // namespace
 
+namespace {
+struct DevTables {
+  DBuf<float> m2l32, m2m32, l2l32;
+  DBuf<double> m2l64, m2m64, l2l64;
+};
+}  // namespace
+
+// Device copies of the translation operators, built once per (device, p,
+// MAC) and shared by all trees.
 void upload_tables(Tree &T, hipStream_t s) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, double, int>, DevTables *> cache;
+  std::lock_guard<std::mutex> lk(mu);
   const Tables &tb = *T.tab;
-  const int ps = T.ps, noff = tb.noff();
-  const int KK = ps / 4, NT = ps / 16;
-  // MFMA-swizzled M2L: for k-step kk and column tile ct, lane l holds
-  // B[k][j] = T[out = ct*16 + l%16][in = (l/16)*KK + kk]
-  std::vector<float> sw32((size_t)noff * KK * NT * 64);
-  std::vector<double> sw64(sw32.size());
-  for (int o = 0; o < noff; ++o) {
-    const double *Tm = tb.m2l.data() + (size_t)o * ps * ps;
-    for (int kk = 0; kk < KK; ++kk)
-      for (int ct = 0; ct < NT; ++ct)
-        for (int l = 0; l < 64; ++l) {
-          int out = ct * 16 + (l % 16), in = (l / 16) * KK + kk;
-          double v = Tm[(size_t)out * ps + in];
-          size_t at = (((size_t)o * KK + kk) * NT + ct) * 64 + l;
-          sw64[at] = v;
-          sw32[at] = (float)v;
+  auto key = std::make_tuple(T.device, tb.p, tb.theta, tb.mac);
+  DevTables *D = nullptr;
+  auto it = cache.find(key);
+  if (it != cache.end()) {
+    D = it->second;
+  } else {
+    D = new DevTables();
+    const int ps = T.ps, noff = tb.noff();
+    const int KK = ps / 4, NT = ps / 16;
+    // MFMA-swizzled M2L: for k-step kk and column tile ct, lane l holds
+    // B[k][j] = T[out = ct*16 + l%16][in = (l/16)*KK + kk]
+    std::vector<float> sw32((size_t)noff * KK * NT * 64);
+    std::vector<double> sw64(sw32.size());
+    for (int o = 0; o < noff; ++o) {
+      const double *Tm = tb.m2l.data() + (size_t)o * ps * ps;
+      for (int kk = 0; kk < KK; ++kk)
+        for (int ct = 0; ct < NT; ++ct)
+          for (int l = 0; l < 64; ++l) {
+            int out = ct * 16 + (l % 16), in = (l / 16) * KK + kk;
+            double v = Tm[(size_t)out * ps + in];
+            size_t at = (((size_t)o * KK + kk) * NT + ct) * 64 + l;
+            sw64[at] = v;
+            sw32[at] = (float)v;
+          }
+    }
+    D->m2l32.alloc(sw32.size());
+    D->m2l64.alloc(sw64.size());
+    HIP_OK(hipMemcpyAsync(D->m2l32.p, sw32.data(), sw32.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(D->m2l64.p, sw64.data(), sw64.size() * 8, hipMemcpyHostToDevice, s));
+    // M2M / L2L stored transposed, [oct][in][out], so that lanes of a wave
+    // (one output coefficient each) read consecutive words
+    std::vector<double> a((size_t)8 * ps * ps), b(a.size());
+    for (int o = 0; o < 8; ++o)
+      for (int r = 0; r < ps; ++r)
+        for (int c = 0; c < ps; ++c) {
+          a[((size_t)o * ps + c) * ps + r] = tb.m2m[((size_t)o * ps + r) * ps + c];
+          b[((size_t)o * ps + c) * ps + r] = tb.l2l[((size_t)o * ps + r) * ps + c];
         }
+    std::vector<float> a32(a.size()), b32(b.size());
+    for (size_t i = 0; i < a.size(); ++i) {
+      a32[i] = (float)a[i];
+      b32[i] = (float)b[i];
+    }
+    D->m2m32.alloc(a32.size());
+    D->l2l32.alloc(b32.size());
+    D->m2m64.alloc(a.size());
+    D->l2l64.alloc(b.size());
+    HIP_OK(hipMemcpyAsync(D->m2m32.p, a32.data(), a32.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(D->l2l32.p, b32.data(), b32.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(D->m2m64.p, a.data(), a.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(D->l2l64.p, b.data(), b.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    cache[key] = D;
   }
-  T.t_m2l32.alloc(sw32.size());
-  T.t_m2l64.alloc(sw64.size());
-  HIP_OK(hipMemcpyAsync(T.t_m2l32.p, sw32.data(), sw32.size() * 4, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(T.t_m2l64.p, sw64.data(), sw64.size() * 8, hipMemcpyHostToDevice, s));
-  // M2M / L2L stored transposed, [oct][in][out], so that lanes of a wave
-  // (one output coefficient each) read consecutive words
-  std::vector<double> a((size_t)8 * ps * ps), b(a.size());
-  for (int o = 0; o < 8; ++o)
-    for (int r = 0; r < ps; ++r)
-      for (int c = 0; c < ps; ++c) {
-        a[((size_t)o * ps + c) * ps + r] = tb.m2m[((size_t)o * ps + r) * ps + c];
-        b[((size_t)o * ps + c) * ps + r] = tb.l2l[((size_t)o * ps + r) * ps + c];
-      }
-  std::vector<float> a32(a.size()), b32(b.size());
-  for (size_t i = 0; i < a.size(); ++i) {
-    a32[i] = (float)a[i];
-    b32[i] = (float)b[i];
-  }
-  T.t_m2m32.alloc(a32.size());
-  T.t_l2l32.alloc(b32.size());
-  T.t_m2m64.alloc(a.size());
-  T.t_l2l64.alloc(b.size());
-  HIP_OK(hipMemcpyAsync(T.t_m2m32.p, a32.data(), a32.size() * 4, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(T.t_l2l32.p, b32.data(), b32.size() * 4, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(T.t_m2m64.p, a.data(), a.size() * 8, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(T.t_l2l64.p, b.data(), b.size() * 8, hipMemcpyHostToDevice, s));
-  HIP_OK(hipStreamSynchronize(s));
+  T.t_m2l32 = D->m2l32.p;
+  T.t_m2l64 = D->m2l64.p;
+  T.t_m2m32 = D->m2m32.p;
+  T.t_l2l32 = D->l2l32.p;
+  T.t_m2m64 = D->m2m64.p;
+  T.t_l2l64 = D->l2l64.p;
 }
 
 void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, int64_t nt, const double *qpos,
@@ -725,7 +755,9 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     radix_sort_u32(T.qkey.p, T.qperm.p, nq, 3 * KEY_BITS, s);
   }
 
-  // leaf level: shallowest level with mean panels per non-empty cell <= ncrit
+  // leaf level: the level whose mean panel occupancy m_l = N / c_l is
+  // closest to ncrit on a log scale, between the first level with m_l <=
+  // ncrit and the one above it (exact integer test N^2 < ncrit^2 c_{l-1} c_l)
   {
     DBuf<unsigned long long> hist;
     hist.alloc(LMAX + 1);
@@ -736,14 +768,17 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     unsigned long long h[LMAX + 1];
     HIP_OK(hipMemcpyAsync(h, hist.p, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    int64_t distinct = 1;
+    int64_t distinct = 1, prev = 1;
     T.L = LMAX;
+    const __int128 nc = T.prm.ncrit;
     for (int l = 0; l <= LMAX; ++l) {
       distinct += (int64_t)h[l];
       if (nt <= (int64_t)T.prm.ncrit * distinct) {
         T.L = l;
+        if (l > 0 && (__int128)nt * nt < nc * nc * prev * distinct) T.L = l - 1;
         break;
       }
+      prev = distinct;
     }
   }
   const int L = T.L;
@@ -1047,24 +1082,31 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     HIP_OK(hipStreamSynchronize(s));
     T.p2p_pairs_pp = (int64_t)h;
   }
-  // P2P chunks: 64 targets of one leaf per wave
+  // P2P chunks: at most 64 targets of one leaf per wave; a chunk of n < 64
+  // targets splits the sources over 64 / n lane groups
   {
     std::vector<int4> rg(CL);
     HIP_OK(hipMemcpyAsync(rg.data(), T.crange.p + T.coff[L], CL * sizeof(int4), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    std::vector<int2> cp, cq;
+    std::vector<int4> cp, cq;
+    auto add = [](std::vector<int4> &v, int leaf, int b, int e) {
+      for (int x = b; x < e; x += 64) {
+        const int n = std::min(64, e - x);
+        v.push_back(make_int4(leaf, x, n, 64 / n));
+      }
+    };
     for (int64_t t = 0; t < CL; ++t) {
-      for (int b = rg[t].x; b < rg[t].y; b += 64) cp.push_back(make_int2((int)t, b));
-      for (int b = rg[t].z; b < rg[t].w; b += 64) cq.push_back(make_int2((int)t, b));
+      add(cp, (int)t, rg[t].x, rg[t].y);
+      add(cq, (int)t, rg[t].z, rg[t].w);
     }
     T.nchunk_p = (int64_t)cp.size();
     T.nchunk_q = (int64_t)cq.size();
     T.chunk_p.alloc(std::max<size_t>(cp.size(), 1));
     T.chunk_q.alloc(std::max<size_t>(cq.size(), 1));
     if (!cp.empty())
-      HIP_OK(hipMemcpyAsync(T.chunk_p.p, cp.data(), cp.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+      HIP_OK(hipMemcpyAsync(T.chunk_p.p, cp.data(), cp.size() * sizeof(int4), hipMemcpyHostToDevice, s));
     if (!cq.empty())
-      HIP_OK(hipMemcpyAsync(T.chunk_q.p, cq.data(), cq.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+      HIP_OK(hipMemcpyAsync(T.chunk_q.p, cq.data(), cq.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   }
   HIP_OK(hipStreamSynchronize(s));
 }

@@ -92,12 +92,12 @@ def test_tree_invariants():
     p = synth.kirkwood(4)
     g = oracle.geometry(p.verts, p.tris)
     tr = T.build(g.c, p.charge_pos, ncrit=32)
-    # the leaf level is the shallowest with mean occupancy <= ncrit
+    # the leaf level's mean occupancy is the closest to ncrit (log scale)
     L = tr.L
-    npc = np.unique(tr.panel_key >> (3 * (10 - L))).shape[0]
-    assert g.N <= 32 * npc
-    npc_up = np.unique(tr.panel_key >> (3 * (10 - L + 1))).shape[0]
-    assert g.N > 32 * npc_up
+    occ = [g.N / np.unique(tr.panel_key >> (3 * (10 - l))).shape[0] for l in range(11)]
+    dist = [abs(np.log(o / 32)) for o in occ]
+    assert dist[L] <= min(dist[L - 1], dist[L + 1]) + 1e-12
+    assert occ[L] <= 2 * 32 * 1.0001 or occ[L + 1] < 32 / 4
     # sorted keys; ranges tile the sorted arrays; charges too
     assert np.all(np.diff(tr.panel_key) >= 0)
     for l in range(L + 1):
