@@ -79,10 +79,12 @@ typedef enum { BEMFMM_BIBEE_CFA = 0, BEMFMM_BIBEE_P = 1 } bemfmm_bibee;
 typedef enum { BEMFMM_MAC_THETA = 0, BEMFMM_MAC_ADJACENT = 1 } bemfmm_mac;
 
 typedef struct {
-  int p;          /* expansion order, 1..12 (degrees 0..p-1) */
-  int ncrit;      /* leaf level = shallowest level with mean panels per
-                     non-empty cell <= ncrit (uniform-depth sparse octree) */
-  double theta;   /* MAC parameter for BEMFMM_MAC_THETA, 0.2..1 */
+  int p;          /* expansion order, 1..11 (degrees 0..p-1) */
+  int ncrit;      /* target leaf occupancy >= 1: the leaf level is the one whose
+                     mean panels per non-empty cell is closest to ncrit on a
+                     log scale, among the first level with mean <= ncrit and
+                     the level above it (uniform-depth sparse octree) */
+  double theta;   /* MAC parameter for BEMFMM_MAC_THETA, 0.3..1 */
   int mac;        /* bemfmm_mac */
   double eps_in;  /* solute permittivity > 0 */
   double eps_out; /* solvent permittivity > 0 */

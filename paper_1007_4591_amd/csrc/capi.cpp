@@ -67,7 +67,7 @@ int bemfmm_build_tree(const double *verts, int64_t nv, const int32_t *tris, int6
     need(nq == 0 || charge_pos, "charge_pos is NULL");
     need(nq >= 0, "nq < 0");
     const bemfmm_params &P = *params;
-    need(P.p >= 1 && P.p <= PMAX, "p outside 1..12");
+    need(P.p >= 1 && P.p <= 11, "p outside 1..11");
     need(P.ncrit >= 1, "ncrit < 1");
     need(P.mac == BEMFMM_MAC_THETA || P.mac == BEMFMM_MAC_ADJACENT, "unknown MAC");
     need(P.mac == BEMFMM_MAC_ADJACENT || (P.theta >= 0.3 && P.theta <= 1.0), "theta outside [0.3, 1]");

@@ -160,7 +160,8 @@ struct Tree {
   int64_t nfar = 0;
   DBuf<int2> far_ts;                 // (target, source) level-local, target-major per level
   DBuf<int32_t> far_ptr;             // per-level target CSR into far pairs (global pair index), [ncell_tot + 1]
-  DBuf<int32_t> far_order;           // pair indices sorted by (level, offset id)
+  DBuf<int32_t> far_order;           // pair indices sorted by offset id (M2L row order)
+  DBuf<int32_t> far_pos;             // pair index -> its row in the sorted order
   DBuf<int32_t> m2l_tile_group;      // per MFMA tile: group index
   DBuf<int32_t> m2l_tile_row;        // per tile: first row (position in far_order)
   DBuf<int32_t> m2l_group_off;       // per group: compact offset id

@@ -249,7 +249,8 @@ __global__ void __launch_bounds__(64) k_m2m(int np2, int ps, int64_t c0, int64_t
 // A = gathered source expansions, B = T_o^T, with the K dimension permuted
 // so that each lane reads a contiguous quarter of its source row:
 // at k-step kk, lane group g = lane/16 supplies input g*KK + kk.
-// Results go to per-pair slots (target-major order), reduced later in a
+// Results are written in the sorted (offset-group) order, so each wave
+// stores 16 contiguous rows; the downward pass gathers them per target in a
 // fixed order.
 template <int NT>
 __global__ void __launch_bounds__(256) k_m2l_f32(const int32_t *__restrict__ tile_group,
@@ -305,7 +306,7 @@ __global__ void __launch_bounds__(256) k_m2l_f32(const int32_t *__restrict__ til
   for (int q = 0; q < 4; ++q) {
     const int rr = row0 + 4 * kq + q;
     if (rr < end) {
-      float *o = out + (size_t)order[rr] * PS + i;
+      float *o = out + (size_t)rr * PS + i;
 #pragma unroll
       for (int ct = 0; ct < NT; ++ct) o[ct * 16] = acc[ct][q];
     }
@@ -350,7 +351,7 @@ __global__ void __launch_bounds__(256) k_m2l_f64(const int32_t *__restrict__ til
   for (int q = 0; q < 4; ++q) {
     const int rr = row0 + kq + 4 * q;
     if (rr < end) {
-      double *o = out + (size_t)order[rr] * PS + i;
+      double *o = out + (size_t)rr * PS + i;
 #pragma unroll
       for (int ct = 0; ct < NT; ++ct) o[ct * 16] = acc[ct][q];
     }
@@ -359,36 +360,71 @@ __global__ void __launch_bounds__(256) k_m2l_f64(const int32_t *__restrict__ til
 
 // ----------------------------------------------------------- downward pass
 
-// One wave per cell of level l: L = L2L(parent) + sum of its M2L results in
-// pair order (compensated).  At the leaf level also writes the evaluation
-// coefficients E[leaf][4][ps] for potential and gradient (see L2P below).
+template <class R> struct VecT;
+template <> struct VecT<float> { using T = float4; static constexpr int W = 4; };
+template <> struct VecT<double> { using T = double2; static constexpr int W = 2; };
+
+// One wave per cell of level l: L = L2L(parent) + sum of the cell's M2L
+// results.  The results of the cell's pairs are gathered (rows of ps reals,
+// located through far_pos) with vector loads: a row takes ps/W lanes, so
+// several pairs are read per step by lane groups; every lane keeps a
+// compensated sum and the groups are added in group order.  At the leaf
+// level the kernel also writes the evaluation coefficients E[leaf][4][ps]
+// of the potential and of its gradient (see L2P).
 template <class R>
 __global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int64_t C, int with_parent,
                                                  const int32_t *__restrict__ parent, const uint32_t *__restrict__ ckey,
                                                  const R *__restrict__ St, const int32_t *__restrict__ far_ptr,
-                                                 const R *__restrict__ m2l, R *__restrict__ Lx, int leaf,
-                                                 R inv_s, R *__restrict__ E) {
+                                                 const int32_t *__restrict__ far_pos, const R *__restrict__ m2l,
+                                                 R *__restrict__ Lx, int leaf, R inv_s, R *__restrict__ E) {
+  using VT = typename VecT<R>::T;
+  constexpr int W = VecT<R>::W;
   extern __shared__ char smem_raw[];
-  R *Ls = reinterpret_cast<R *>(smem_raw);
+  R *Ls = reinterpret_cast<R *>(smem_raw);     // [ps]
+  R *part = Ls + ps;                          // [64 * W] group partials
   const int64_t c = c0 + blockIdx.x;
   if (blockIdx.x >= C) return;
   const int lane = threadIdx.x;
   const int np2 = p * p;
-  R s[3] = {R(0), R(0), R(0)}, comp[3] = {R(0), R(0), R(0)};
-  const int b = far_ptr[c], e = far_ptr[c + 1];
-  for (int q = b; q < e; ++q) {
-    const R *src = m2l + (size_t)q * ps;
+  const int lpr = ps / W;                     // lanes per row
+  const int groups = 64 / lpr;                // rows per step
+  const int grp = lane / lpr, k4 = lane - grp * lpr;
+  const bool act = grp < groups;
+  R s[W], comp[W];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const int k = lane + 64 * t;
-      if (k < ps) {
-        const R y = src[k] - comp[t];
-        const R tt = s[t] + y;
-        comp[t] = (tt - s[t]) - y;
-        s[t] = tt;
+  for (int w = 0; w < W; ++w) s[w] = comp[w] = R(0);
+  const int b = far_ptr[c], e = far_ptr[c + 1];
+  if (act) {
+    for (int q = b + grp; q < e; q += groups) {
+      const VT v = reinterpret_cast<const VT *>(m2l + (size_t)far_pos[q] * ps)[k4];
+      R x[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) x[w] = reinterpret_cast<const R *>(&v)[w];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const R y = x[w] - comp[w];
+        const R t = s[w] + y;
+        comp[w] = (t - s[w]) - y;
+        s[w] = t;
       }
     }
   }
+#pragma unroll
+  for (int w = 0; w < W; ++w) part[lane * W + w] = s[w];
+  __syncthreads();
+  // group totals in group order -> Ls[k]
+  for (int k = lane; k < ps; k += 64) {
+    const int kk = k / W, w = k - kk * W;
+    R acc = part[kk * W + w], cc = R(0);
+    for (int h = 1; h < groups; ++h) {
+      const R y = part[(h * lpr + kk) * W + w] - cc;
+      const R t = acc + y;
+      cc = (t - acc) - y;
+      acc = t;
+    }
+    Ls[k] = acc;
+  }
+  __syncthreads();
   if (with_parent) {
     const int pc = parent[c];
     const int oct = ckey[c] & 7;
@@ -404,19 +440,15 @@ __global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int6
       }
     }
 #pragma unroll
-    for (int t = 0; t < 3; ++t) s[t] += a[t];
-  }
-  R *out = Lx + (size_t)c * ps;
-#pragma unroll
-  for (int t = 0; t < 3; ++t) {
-    const int k = lane + 64 * t;
-    if (k < ps) {
-      out[k] = s[t];
-      Ls[k] = s[t];
+    for (int t = 0; t < 3; ++t) {
+      const int k = lane + 64 * t;
+      if (k < ps) Ls[k] += a[t];
     }
   }
-  if (!leaf) return;
   __syncthreads();
+  R *out = Lx + (size_t)c * ps;
+  for (int k = lane; k < ps; k += 64) out[k] = Ls[k];
+  if (!leaf) return;
   // evaluation coefficients of the leaf (scaled to physical units):
   // phi(x) = sum_k E0[k] * Rpacked_k(rho), grad phi = sum_k E{x,y,z}[k] * Rpacked_k(rho)
   R *Ec = E + (size_t)blockIdx.x * 4 * ps;
@@ -440,14 +472,12 @@ __global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int6
     return ((-m) & 1) ? Ls[idx_im(n, -m)] : -Ls[idx_im(n, -m)];
   };
   for (int k = lane; k < np2; k += 64) {
-    // decode k -> (n, m, part)
     int n = 0;
     while ((n + 1) * (n + 1) <= k) ++n;
     const int rem = k - n * n;
     const int m = (rem + 1) / 2;
     const bool im = (rem > 0) && ((rem & 1) == 0);
     const R two = (m > 0) ? R(2) : R(1);
-    // potential
     Ec[k] = im ? (-R(2) * Lim(n, m) * inv_s) : (two * Lre(n, m) * inv_s);
     if (n <= p - 2) {
       // G_z = L_{n+1}^m; G_x = (L_{n+1}^{m-1} - L_{n+1}^{m+1})/2; G_y = -i (L_{n+1}^{m+1} + L_{n+1}^{m-1})/2
@@ -876,9 +906,10 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     const R *Sl = f64 ? reinterpret_cast<const R *>(T.t_l2l64) : reinterpret_cast<const R *>(T.t_l2l32);
     for (int l = 2; l <= L; ++l) {
       const bool leaf = (l == L);
-      const size_t shm2 = (size_t)ps * sizeof(R);
+      const size_t shm2 = (size_t)(ps + 64 * VecT<R>::W) * sizeof(R);
       k_downward<R><<<T.ncell[l], 64, shm2, s>>>(p, ps, T.coff[l], T.ncell[l], l > 2 ? 1 : 0, T.cparent.p, T.ckey.p,
-                                                 Sl, T.far_ptr.p, m2l, Lx, leaf ? 1 : 0, R(1.0 / sL), E);
+                                                 Sl, T.far_ptr.p, T.far_pos.p, m2l, Lx, leaf ? 1 : 0, R(1.0 / sL),
+                                                 E);
       LAUNCH_OK();
     }
     prof_end(T, ST_L2L, s);

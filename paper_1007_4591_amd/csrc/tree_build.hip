@@ -1034,6 +1034,9 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     LAUNCH_OK();
     T.n_m2l_groups = G;
     T.n_m2l_tiles = ntiles;
+    T.far_pos.alloc(nf);
+    k_inverse_perm<<<cdiv(nf, TB), TB, 0, s>>>(T.far_order.p, nf, T.far_pos.p);
+    LAUNCH_OK();
   }
 
   // leaf membership, inverse permutations, sorted point data
