@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=4096)
     ap.add_argument("--matvec-reps", type=int, default=20)
+    ap.add_argument("--calib-copy-mb", type=int, default=256,
+                    help="size of a plain device copy run before the matvecs, the reference kernel for "
+                         "hardware byte counters")
     return ap.parse_args()
 
 
@@ -91,6 +94,15 @@ def main():
     tree, x, sinfo, ainfo, dG, bib = last
     print(f"[bench] step {ms_per_step:.2f} ms dG={dG:.6f} bibee={bib:.6f} solve iters={sinfo.iters} "
           f"outer={sinfo.outer_iters} adjoint iters={ainfo.iters}", file=sys.stderr, flush=True)
+
+    # ---- a plain copy of known size (reference for FETCH_SIZE / WRITE_SIZE)
+    if args.calib_copy_mb > 0:
+        nel = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- matvec throughput and stage profile (HIP events on the stream)
     rng = np.random.default_rng(1)

@@ -16,6 +16,8 @@
 #include <stdint.h>
 
 #include <cstddef>
+#include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -26,6 +28,9 @@ namespace bemfmm {
 constexpr int KEY_BITS = 10;  // bits per axis of the Morton keys (30-bit keys)
 constexpr int LMAX = KEY_BITS;
 constexpr int PMAX = 12;
+// M2L work tiles: 4 waves x RT row tiles of 16 pairs
+constexpr int M2L_RT32 = 4, M2L_RT64 = 2;
+constexpr int M2L_ROWS32 = 4 * M2L_RT32 * 16, M2L_ROWS64 = 4 * M2L_RT64 * 16;
 constexpr double PI = 3.14159265358979323846;
 constexpr double K_COULOMB = 332.06;
 
@@ -162,8 +167,10 @@ struct Tree {
   DBuf<int32_t> far_ptr;             // per-level target CSR into far pairs (global pair index), [ncell_tot + 1]
   DBuf<int32_t> far_order;           // pair indices sorted by offset id (M2L row order)
   DBuf<int32_t> far_pos;             // pair index -> its row in the sorted order
-  DBuf<int32_t> m2l_tile_group;      // per MFMA tile: group index
+  DBuf<int32_t> m2l_tile_group;      // per FP32 MFMA tile (M2L_ROWS32 rows): group index
   DBuf<int32_t> m2l_tile_row;        // per tile: first row (position in far_order)
+  DBuf<int32_t> m2l_tile_group64, m2l_tile_row64;  // the same for FP64 tiles (M2L_ROWS64 rows)
+  int64_t n_m2l_tiles64 = 0;
   DBuf<int32_t> m2l_group_off;       // per group: compact offset id
   DBuf<int32_t> m2l_group_end;       // per group: end position in far_order
   int64_t n_m2l_tiles = 0, n_m2l_groups = 0;
@@ -184,11 +191,14 @@ struct Tree {
 
   PrecBufs *pb32 = nullptr, *pb64 = nullptr;
 
-  // solver scratch (FP64, user order)
-  DBuf<double> wrk;      // general vectors
-  DBuf<double> gm_V;     // GMRES basis
-  DBuf<double> red;      // reduction scratch
-  DBuf<double> hred;     // pinned? (device) dot results
+  // persistent FP64 work vectors of the solvers, by purpose (grow only)
+  std::map<std::string, std::unique_ptr<DBuf<double>>> work;
+  double *buf(const std::string &name, size_t n) {
+    auto &b = work[name];
+    if (!b) b.reset(new DBuf<double>());
+    b->reserve(std::max<size_t>(n, 1));
+    return b->p;
+  }
 
   // stage profiling
   bool prof = false;

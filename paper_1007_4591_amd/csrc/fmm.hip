@@ -243,16 +243,21 @@ __global__ void __launch_bounds__(64) k_m2m(int np2, int ps, int64_t c0, int64_t
 
 // -------------------------------------------------------------------- M2L
 
-// Offset-grouped dense M2L on MFMA.  Work tile = 64 consecutive pairs of one
-// offset group (4 waves x 16 pairs).  For each wave:
-//   D[16 pairs x 16*NT outputs] = A[16 x ps] * B[ps x 16*NT],
-// A = gathered source expansions, B = T_o^T, with the K dimension permuted
-// so that each lane reads a contiguous quarter of its source row:
-// at k-step kk, lane group g = lane/16 supplies input g*KK + kk.
+// Offset-grouped dense M2L on MFMA.  A work tile is 4 waves x RT x 16
+// consecutive pairs of one offset group (pairs are sorted by offset, all
+// levels together: the scaled operator depends on the offset only).  Each
+// wave computes, for RT row tiles of 16 pairs,
+//   D[16 x 16*NT] += A[16 x 4] * B[4 x 16*NT]   for every k-step,
+// A = gathered source expansions, B = T_o^T read once per k-step and reused
+// by the RT row tiles.  The K dimension is permuted so that each lane reads
+// a contiguous quarter of its source row: at k-step kk, lane group
+// g = lane/16 supplies input g*KK + kk (the B table is stored in that order).
 // Results are written in the sorted (offset-group) order, so each wave
-// stores 16 contiguous rows; the downward pass gathers them per target in a
-// fixed order.
-template <int NT>
+// stores RT*16 contiguous rows; the downward pass gathers them per target in
+// a fixed order.  Output layouts (checked on the device): FP32 16x16x4 puts
+// D[4*(lane/16) + q][lane%16] in register q; FP64 16x16x4 puts
+// D[lane/16 + 4*q][lane%16] in register q.
+template <int NT, int RT>
 __global__ void __launch_bounds__(256) k_m2l_f32(const int32_t *__restrict__ tile_group,
                                                  const int32_t *__restrict__ tile_row,
                                                  const int32_t *__restrict__ group_off,
@@ -266,54 +271,60 @@ __global__ void __launch_bounds__(256) k_m2l_f32(const int32_t *__restrict__ til
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = tile_group[tile];
   const int end = group_end[g];
-  const int row0 = tile_row[tile] + wave * 16;
+  const int row0 = tile_row[tile] + wave * (16 * RT);
   if (row0 >= end) return;
   const int off = group_off[g];
   const int i = lane & 15, kq = lane >> 4;
-  // A operand: this lane's quarter of its pair's source row
-  float a[KK];
-  const int r = row0 + i;
-  if (r < end) {
-    const int pair = order[r];
-    const int src = ts[pair].y;
-    const float4 *Ms = reinterpret_cast<const float4 *>(M + (size_t)src * PS + kq * KK);
+  // A operands: this lane's quarter of the source row of each row tile
+  float a[RT][KK];
 #pragma unroll
-    for (int v = 0; v < KK / 4; ++v) {
-      const float4 t = Ms[v];
-      a[4 * v] = t.x;
-      a[4 * v + 1] = t.y;
-      a[4 * v + 2] = t.z;
-      a[4 * v + 3] = t.w;
+  for (int rt = 0; rt < RT; ++rt) {
+    const int r = row0 + rt * 16 + i;
+    if (r < end) {
+      const int src = ts[order[r]].y;
+      const float4 *Ms = reinterpret_cast<const float4 *>(M + (size_t)src * PS + kq * KK);
+#pragma unroll
+      for (int v = 0; v < KK / 4; ++v) {
+        const float4 t = Ms[v];
+        a[rt][4 * v] = t.x;
+        a[rt][4 * v + 1] = t.y;
+        a[rt][4 * v + 2] = t.z;
+        a[rt][4 * v + 3] = t.w;
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < KK; ++v) a[rt][v] = 0.f;
     }
-  } else {
-#pragma unroll
-    for (int v = 0; v < KK; ++v) a[v] = 0.f;
   }
-  f32x4 acc[NT];
+  f32x4 acc[RT][NT];
 #pragma unroll
-  for (int ct = 0; ct < NT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
   const float *B = Tsw + (size_t)off * KK * NT * 64 + lane;
 #pragma unroll
   for (int kk = 0; kk < KK; ++kk) {
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) {
       const float b = B[(kk * NT + ct) * 64];
-      acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b, acc[ct], 0, 0, 0);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][kk], b, acc[rt][ct], 0, 0, 0);
     }
   }
-  // D[row = 4*(lane/16) + q][col = ct*16 + lane%16]
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int rr = row0 + 4 * kq + q;
-    if (rr < end) {
-      float *o = out + (size_t)rr * PS + i;
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < NT; ++ct) o[ct * 16] = acc[ct][q];
+    for (int q = 0; q < 4; ++q) {
+      const int rr = row0 + rt * 16 + 4 * kq + q;
+      if (rr < end) {
+        float *o = out + (size_t)rr * PS + i;
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) o[ct * 16] = acc[rt][ct][q];
+      }
     }
-  }
 }
 
-template <int NT>
+template <int NT, int RT>
 __global__ void __launch_bounds__(256) k_m2l_f64(const int32_t *__restrict__ tile_group,
                                                  const int32_t *__restrict__ tile_row,
                                                  const int32_t *__restrict__ group_off,
@@ -327,35 +338,44 @@ __global__ void __launch_bounds__(256) k_m2l_f64(const int32_t *__restrict__ til
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = tile_group[tile];
   const int end = group_end[g];
-  const int row0 = tile_row[tile] + wave * 16;
+  const int row0 = tile_row[tile] + wave * (16 * RT);
   if (row0 >= end) return;
   const int off = group_off[g];
   const int i = lane & 15, kq = lane >> 4;
-  const int r = row0 + i;
-  const double *Ms = nullptr;
-  if (r < end) Ms = M + (size_t)ts[order[r]].y * PS + kq * KK;
-  f64x4 acc[NT];
+  const double *Ms[RT];
 #pragma unroll
-  for (int ct = 0; ct < NT; ++ct) acc[ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int rt = 0; rt < RT; ++rt) {
+    const int r = row0 + rt * 16 + i;
+    Ms[rt] = (r < end) ? M + (size_t)ts[order[r]].y * PS + kq * KK : nullptr;
+  }
+  f64x4 acc[RT][NT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
   const double *B = Tsw + (size_t)off * KK * NT * 64 + lane;
   for (int kk = 0; kk < KK; ++kk) {
-    const double av = Ms ? Ms[kk] : 0.0;
+    double av[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) av[rt] = Ms[rt] ? Ms[rt][kk] : 0.0;
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) {
       const double b = B[(kk * NT + ct) * 64];
-      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[ct], 0, 0, 0);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rt], b, acc[rt][ct], 0, 0, 0);
     }
   }
-  // FP64 layout: D[row = lane/16 + 4*q][col = ct*16 + lane%16]
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int rr = row0 + kq + 4 * q;
-    if (rr < end) {
-      double *o = out + (size_t)rr * PS + i;
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < NT; ++ct) o[ct * 16] = acc[ct][q];
+    for (int q = 0; q < 4; ++q) {
+      const int rr = row0 + rt * 16 + kq + 4 * q;
+      if (rr < end) {
+        double *o = out + (size_t)rr * PS + i;
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) o[ct * 16] = acc[rt][ct][q];
+      }
     }
-  }
 }
 
 // ----------------------------------------------------------- downward pass
@@ -872,17 +892,16 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     prof_begin(T, ST_M2L, s);
     const int NT = ps / 16;
     if (T.n_m2l_tiles > 0) {
-      const dim3 grid((unsigned)T.n_m2l_tiles);
 #define M2L_CASE(nt)                                                                                           \
   case nt:                                                                                                     \
     if (f64)                                                                                                   \
-      k_m2l_f64<nt><<<grid, 256, 0, s>>>(T.m2l_tile_group.p, T.m2l_tile_row.p, T.m2l_group_off.p,              \
-                                         T.m2l_group_end.p, T.far_order.p, T.far_ts.p, T.t_m2l64,           \
-                                         reinterpret_cast<const double *>(M), reinterpret_cast<double *>(m2l)); \
+      k_m2l_f64<nt, M2L_RT64><<<dim3((unsigned)T.n_m2l_tiles64), 256, 0, s>>>(                                 \
+          T.m2l_tile_group64.p, T.m2l_tile_row64.p, T.m2l_group_off.p, T.m2l_group_end.p, T.far_order.p,       \
+          T.far_ts.p, T.t_m2l64, reinterpret_cast<const double *>(M), reinterpret_cast<double *>(m2l));        \
     else                                                                                                       \
-      k_m2l_f32<nt><<<grid, 256, 0, s>>>(T.m2l_tile_group.p, T.m2l_tile_row.p, T.m2l_group_off.p,              \
-                                         T.m2l_group_end.p, T.far_order.p, T.far_ts.p, T.t_m2l32,           \
-                                         reinterpret_cast<const float *>(M), reinterpret_cast<float *>(m2l));  \
+      k_m2l_f32<nt, M2L_RT32><<<dim3((unsigned)T.n_m2l_tiles), 256, 0, s>>>(                                   \
+          T.m2l_tile_group.p, T.m2l_tile_row.p, T.m2l_group_off.p, T.m2l_group_end.p, T.far_order.p,           \
+          T.far_ts.p, T.t_m2l32, reinterpret_cast<const float *>(M), reinterpret_cast<float *>(m2l));          \
     break;
       switch (NT) {
         M2L_CASE(1)
@@ -893,7 +912,6 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
         M2L_CASE(6)
         M2L_CASE(7)
         M2L_CASE(8)
-        M2L_CASE(9)
         default:
           BF_THROW(BEMFMM_EINVAL, "unsupported expansion order");
       }

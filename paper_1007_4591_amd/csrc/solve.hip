@@ -115,9 +115,19 @@ __global__ void k_adjoint_out(const double *__restrict__ pg, const double *__res
   }
 }
 
+// reduction scratch (device): partial sums and one result slot
+// Each call site passes its own tag, so nested users never share (and
+// never reallocate) the same scratch.
 struct Ws {
-  DBuf<double> partial, h, tmp;
-  int nb = 0;
+  double *partial = nullptr, *h = nullptr;
+  size_t cap = 0;
+  Ws(Tree &T, size_t nvec, const char *tag) {
+    cap = (size_t)std::max(1, std::min(512, (int)((T.N + 4 * 256 - 1) / (4 * 256)))) * std::max<size_t>(nvec, 1);
+    const int64_t nmax = std::max<int64_t>(T.N, T.Q);
+    cap = std::max(cap, (size_t)std::max(1, std::min(512, (int)((nmax + 1023) / 1024))) * std::max<size_t>(nvec, 1));
+    partial = T.buf(std::string("wsp_") + tag, cap);
+    h = T.buf(std::string("wsh_") + tag, 4);
+  }
 };
 
 int nblocks_for(int64_t n) { return std::max(1, std::min(512, cdiv(n, 4 * RB))); }
@@ -126,18 +136,17 @@ int nblocks_for(int64_t n) { return std::max(1, std::min(512, cdiv(n, 4 * RB)));
 void dots(Ws &ws, const double *V, int64_t ld, int k, const double *w, int64_t n, double *out_dev, int accumulate,
           hipStream_t s) {
   const int nb = nblocks_for(n);
-  ws.partial.reserve((size_t)nb * std::max(k, 1));
-  k_dots<<<dim3(nb, k), RB, 0, s>>>(V, ld, w, n, nb, ws.partial.p);
+  if ((size_t)nb * std::max(k, 1) > ws.cap) BF_THROW(BEMFMM_EDEVICE, "reduction scratch too small");
+  k_dots<<<dim3(nb, k), RB, 0, s>>>(V, ld, w, n, nb, ws.partial);
   LAUNCH_OK();
-  k_reduce<<<k, RB, 0, s>>>(ws.partial.p, nb, out_dev, accumulate);
+  k_reduce<<<k, RB, 0, s>>>(ws.partial, nb, out_dev, accumulate);
   LAUNCH_OK();
 }
 
 double dot_host(Ws &ws, const double *a, const double *b, int64_t n, hipStream_t s) {
-  ws.h.reserve(1);
-  dots(ws, a, n, 1, b, n, ws.h.p, 0, s);
+  dots(ws, a, n, 1, b, n, ws.h, 0, s);
   double v = 0.0;
-  HIP_OK(hipMemcpyAsync(&v, ws.h.p, 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&v, ws.h, 8, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   return v;
 }
@@ -153,15 +162,9 @@ GmresOut gmres(Tree &T, int op, int prec, const double *b, double *x, double tol
                hipStream_t s) {
   const int64_t n = T.N;
   const int m = std::max(1, std::min(restart > 0 ? restart : 30, maxit > 0 ? maxit : 1));
-  Ws ws;
-  DBuf<double> V, w, hd, yv, r, ax;
-  V.alloc((size_t)(m + 1) * n);
-  w.alloc(n);
-  hd.alloc(2 * (m + 2));
-  yv.alloc(m + 1);
-  r.alloc(n);
-  ax.alloc(n);
-  ws.partial.reserve((size_t)nblocks_for(n) * (m + 2));
+  Ws ws(T, m + 2, "gmres");
+  struct { double *p; } V{T.buf("gm_V", (size_t)(m + 1) * n)}, w{T.buf("gm_w", n)}, hd{T.buf("gm_hd", 2 * (m + 2))},
+      yv{T.buf("gm_y", m + 1)}, r{T.buf("gm_r", n)}, ax{T.buf("gm_ax", n)};
   HIP_OK(hipMemsetAsync(x, 0, n * 8, s));
   GmresOut out;
   const double bnorm = std::sqrt(dot_host(ws, b, b, n, s));
@@ -245,23 +248,21 @@ GmresOut gmres(Tree &T, int op, int prec, const double *b, double *x, double tol
   return out;
 }
 
-double rel_residual64(Tree &T, int op, const double *b, const double *x, double bnorm, hipStream_t s,
-                      DBuf<double> &tmp) {
-  Ws ws;
+double rel_residual64(Tree &T, int op, const double *b, const double *x, double bnorm, hipStream_t s) {
+  Ws ws(T, 1, "resid");
   const int64_t n = T.N;
-  tmp.reserve(n);
-  op_apply(T, op, BEMFMM_FP64, x, tmp.p, s);
-  k_sub<<<cdiv(n, 256), 256, 0, s>>>(tmp.p, b, tmp.p, n);
+  double *tmp = T.buf("res_tmp", n);
+  op_apply(T, op, BEMFMM_FP64, x, tmp, s);
+  k_sub<<<cdiv(n, 256), 256, 0, s>>>(tmp, b, tmp, n);
   LAUNCH_OK();
-  return std::sqrt(dot_host(ws, tmp.p, tmp.p, n, s)) / bnorm;
+  return std::sqrt(dot_host(ws, tmp, tmp, n, s)) / bnorm;
 }
 
 // Solve op x = b (op = A or A^T) at the requested precision; fills info.
 void solve_op(Tree &T, int op, const double *b, double *x, double tol, int maxit, int restart, int precision,
               bemfmm_solve_info *info, hipStream_t s) {
   const int64_t n = T.N;
-  Ws ws;
-  DBuf<double> tmp;
+  Ws ws(T, 1, "solve");
   const double bnorm = std::sqrt(dot_host(ws, b, b, n, s));
   bemfmm_solve_info inf{};
   inf.outer_iters = 1;
@@ -275,15 +276,13 @@ void solve_op(Tree &T, int op, const double *b, double *x, double tol, int maxit
   if (precision != BEMFMM_FP32_REFINED) {
     GmresOut g = gmres(T, op, precision, b, x, tol, maxit, restart, s);
     inf.iters = g.iters;
-    inf.rel_residual = rel_residual64(T, op, b, x, bnorm, s, tmp);
+    inf.rel_residual = rel_residual64(T, op, b, x, bnorm, s);
     inf.converged = inf.rel_residual <= tol;
     if (info) *info = inf;
     return;
   }
   // iterative refinement: FP64 residual, FP32-operator correction
-  DBuf<double> r, d;
-  r.alloc(n);
-  d.alloc(n);
+  struct { double *p; } r{T.buf("ir_r", n)}, d{T.buf("ir_d", n)}, tmp{T.buf("ir_tmp", n)};
   HIP_OK(hipMemsetAsync(x, 0, n * 8, s));
   HIP_OK(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
   double rn = bnorm;
@@ -297,7 +296,6 @@ void solve_op(Tree &T, int op, const double *b, double *x, double tol, int maxit
     ++inf.outer_iters;
     k_axpy<<<cdiv(n, 256), 256, 0, s>>>(x, d.p, 1.0, n);
     LAUNCH_OK();
-    tmp.reserve(n);
     op_apply(T, op, BEMFMM_FP64, x, tmp.p, s);
     k_sub<<<cdiv(n, 256), 256, 0, s>>>(r.p, b, tmp.p, n);
     LAUNCH_OK();
@@ -348,8 +346,7 @@ void op_apply(Tree &T, int op, int precision, const double *x, double *y, hipStr
 }
 
 double dot_d(Tree &T, const double *a, const double *b, int64_t n, hipStream_t s) {
-  (void)T;
-  Ws ws;
+  Ws ws(T, 1, "dot");
   return dot_host(ws, a, b, n, s);
 }
 
@@ -358,8 +355,7 @@ void solve_bem(Tree &T, const double *q, double *x, double tol, int maxit, int r
   auto t0 = std::chrono::steady_clock::now();
   const int64_t n = T.N;
   const double f = 1.0 - T.prm.eps_in / T.prm.eps_out;
-  DBuf<double> b;
-  b.alloc(n);
+  struct { double *p; } b{T.buf("sv_b", n)};
   // right-hand side f E with E = B q (FP64 operator unless plain FP32)
   op_apply(T, BEMFMM_OP_B, precision == BEMFMM_FP32 ? BEMFMM_FP32 : BEMFMM_FP64, q, b.p, s);
   k_scale<<<cdiv(n, 256), 256, 0, s>>>(b.p, b.p, f, n);
@@ -374,8 +370,7 @@ void solve_bem(Tree &T, const double *q, double *x, double tol, int maxit, int r
 
 double energy(Tree &T, const double *q, const double *x, int precision, hipStream_t s) {
   if (T.Q == 0) return 0.0;
-  DBuf<double> phi;
-  phi.alloc(T.Q);
+  struct { double *p; } phi{T.buf("en_phi", T.Q)};
   op_apply(T, BEMFMM_OP_C, precision, x, phi.p, s);
   const double kappa = 2.0 * PI * K_COULOMB / T.prm.eps_in;
   return kappa * dot_d(T, q, phi.p, T.Q, s);
@@ -384,8 +379,7 @@ double energy(Tree &T, const double *q, const double *x, int precision, hipStrea
 double bibee(Tree &T, const double *q, int kind, int precision, hipStream_t s) {
   const int64_t n = T.N;
   const double f = 1.0 - T.prm.eps_in / T.prm.eps_out;
-  DBuf<double> xh;
-  xh.alloc(n);
+  struct { double *p; } xh{T.buf("bb_x", n)};
   op_apply(T, BEMFMM_OP_B, precision, q, xh.p, s);
   const double scale = (kind == BEMFMM_BIBEE_P) ? f / (1.0 - 0.5 * f) : f;
   k_scale<<<cdiv(n, 256), 256, 0, s>>>(xh.p, xh.p, scale, n);
@@ -404,11 +398,7 @@ void adjoint(Tree &T, const double *q, const double *x, double tol, int maxit, i
     if (info) *info = inf;
     return;
   }
-  DBuf<double> ct, y, fy, pg;
-  ct.alloc(n);
-  y.alloc(n);
-  fy.alloc(n);
-  pg.alloc(4 * Q);
+  struct { double *p; } ct{T.buf("ad_ct", n)}, y{T.buf("ad_y", n)}, fy{T.buf("ad_fy", n)}, pg{T.buf("ad_pg", 4 * Q)};
   // A^T y = C^T q
   op_apply(T, BEMFMM_OP_CT, precision == BEMFMM_FP32 ? BEMFMM_FP32 : BEMFMM_FP64, q, ct.p, s);
   solve_op(T, BEMFMM_OP_AT, ct.p, y.p, tol, maxit, restart, precision, &inf, s);

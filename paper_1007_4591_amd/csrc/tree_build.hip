@@ -1018,22 +1018,25 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     k_group_make<<<cdiv(nf, TB), TB, 0, s>>>(key.p, nf, flag.p, pos.p, T.m2l_group_off.p, gbeg.p,
                                              T.m2l_group_end.p);
     LAUNCH_OK();
-    const int ROWS = 64;  // pairs per M2L workgroup tile
-    DBuf<int32_t> ntile, tpos;
-    ntile.alloc(G + 1);
-    tpos.alloc(G + 1);
-    k_group_tiles<<<cdiv(G, TB), TB, 0, s>>>(gbeg.p, T.m2l_group_end.p, G, ROWS, ntile.p);
-    LAUNCH_OK();
-    HIP_OK(hipMemsetAsync(ntile.p + G, 0, 4, s));
-    int32_t ntiles = 0;
-    exclusive_scan_i32(ntile.p, tpos.p, G + 1, s, &ntiles);
-    T.m2l_tile_group.alloc(ntiles);
-    T.m2l_tile_row.alloc(ntiles);
-    k_tile_list<<<cdiv(G, TB), TB, 0, s>>>(gbeg.p, T.m2l_group_end.p, G, ROWS, tpos.p, T.m2l_tile_group.p,
-                                           T.m2l_tile_row.p);
-    LAUNCH_OK();
+    for (int pass = 0; pass < 2; ++pass) {
+      const int ROWS = pass == 0 ? M2L_ROWS32 : M2L_ROWS64;
+      DBuf<int32_t> ntile, tpos;
+      ntile.alloc(G + 1);
+      tpos.alloc(G + 1);
+      k_group_tiles<<<cdiv(G, TB), TB, 0, s>>>(gbeg.p, T.m2l_group_end.p, G, ROWS, ntile.p);
+      LAUNCH_OK();
+      HIP_OK(hipMemsetAsync(ntile.p + G, 0, 4, s));
+      int32_t ntiles = 0;
+      exclusive_scan_i32(ntile.p, tpos.p, G + 1, s, &ntiles);
+      DBuf<int32_t> &tg = pass == 0 ? T.m2l_tile_group : T.m2l_tile_group64;
+      DBuf<int32_t> &tr = pass == 0 ? T.m2l_tile_row : T.m2l_tile_row64;
+      tg.alloc(ntiles);
+      tr.alloc(ntiles);
+      k_tile_list<<<cdiv(G, TB), TB, 0, s>>>(gbeg.p, T.m2l_group_end.p, G, ROWS, tpos.p, tg.p, tr.p);
+      LAUNCH_OK();
+      (pass == 0 ? T.n_m2l_tiles : T.n_m2l_tiles64) = ntiles;
+    }
     T.n_m2l_groups = G;
-    T.n_m2l_tiles = ntiles;
     T.far_pos.alloc(nf);
     k_inverse_perm<<<cdiv(nf, TB), TB, 0, s>>>(T.far_order.p, nf, T.far_pos.p);
     LAUNCH_OK();
