@@ -165,15 +165,19 @@ struct Tree {
   int64_t nfar = 0;
   DBuf<int2> far_ts;                 // (target, source) level-local, target-major per level
   DBuf<int32_t> far_ptr;             // per-level target CSR into far pairs (global pair index), [ncell_tot + 1]
-  DBuf<int32_t> far_order;           // pair indices sorted by offset id (M2L row order)
-  DBuf<int32_t> far_pos;             // pair index -> its row in the sorted order
-  DBuf<int32_t> m2l_tile_group;      // per FP32 MFMA tile (M2L_ROWS32 rows): group index
-  DBuf<int32_t> m2l_tile_row;        // per tile: first row (position in far_order)
-  DBuf<int32_t> m2l_tile_group64, m2l_tile_row64;  // the same for FP64 tiles (M2L_ROWS64 rows)
-  int64_t n_m2l_tiles64 = 0;
-  DBuf<int32_t> m2l_group_off;       // per group: compact offset id
-  DBuf<int32_t> m2l_group_end;       // per group: end position in far_order
-  int64_t n_m2l_tiles = 0, n_m2l_groups = 0;
+  // M2L work lists, one per (source kind, target kind): 0 panels -> panels,
+  // 1 charges -> panels, 2 panels -> charges.  Only pairs whose source cell
+  // holds sources and whose target cell holds targets of that kind are kept;
+  // they are sorted by translation offset (all levels together).
+  struct M2LList {
+    DBuf<int32_t> order;             // kept pair indices, offset-sorted (= M2L output row order)
+    DBuf<int32_t> pos;               // pair index -> output row, or -1 if not kept
+    DBuf<int32_t> group_off;         // per offset group: compact offset id
+    DBuf<int32_t> group_end;         // per group: end row
+    DBuf<int32_t> tile_group, tile_row;      // FP32 tiles of M2L_ROWS32 rows
+    DBuf<int32_t> tile_group64, tile_row64;  // FP64 tiles of M2L_ROWS64 rows
+    int64_t n = 0, ngroups = 0, ntiles = 0, ntiles64 = 0;
+  } m2l[3];
   int64_t p2p_pairs_pp = 0;
 
   // translation tables on the device, shared by every tree with the same

@@ -416,7 +416,9 @@ __global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int6
   const int b = far_ptr[c], e = far_ptr[c + 1];
   if (act) {
     for (int q = b + grp; q < e; q += groups) {
-      const VT v = reinterpret_cast<const VT *>(m2l + (size_t)far_pos[q] * ps)[k4];
+      const int row = far_pos[q];
+      if (row < 0) continue;  // pair not in this product's list
+      const VT v = reinterpret_cast<const VT *>(m2l + (size_t)row * ps)[k4];
       R x[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) x[w] = reinterpret_cast<const R *>(&v)[w];
@@ -875,6 +877,8 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   }
   prof_end(T, ST_OTHER, s);
 
+  const int combo = src_charges ? 1 : (rq.tgt == TGT_CHARGE ? 2 : 0);
+  const Tree::M2LList &ML = T.m2l[combo];
   const bool far = (L >= 2) && T.nfar > 0;
   if (far) {
     prof_begin(T, ST_P2M, s);
@@ -891,17 +895,17 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     // M2L, every level in one launch
     prof_begin(T, ST_M2L, s);
     const int NT = ps / 16;
-    if (T.n_m2l_tiles > 0) {
+    if (ML.n > 0) {
 #define M2L_CASE(nt)                                                                                           \
   case nt:                                                                                                     \
     if (f64)                                                                                                   \
-      k_m2l_f64<nt, M2L_RT64><<<dim3((unsigned)T.n_m2l_tiles64), 256, 0, s>>>(                                 \
-          T.m2l_tile_group64.p, T.m2l_tile_row64.p, T.m2l_group_off.p, T.m2l_group_end.p, T.far_order.p,       \
-          T.far_ts.p, T.t_m2l64, reinterpret_cast<const double *>(M), reinterpret_cast<double *>(m2l));        \
+      k_m2l_f64<nt, M2L_RT64><<<dim3((unsigned)ML.ntiles64), 256, 0, s>>>(                                     \
+          ML.tile_group64.p, ML.tile_row64.p, ML.group_off.p, ML.group_end.p, ML.order.p, T.far_ts.p,          \
+          T.t_m2l64, reinterpret_cast<const double *>(M), reinterpret_cast<double *>(m2l));                    \
     else                                                                                                       \
-      k_m2l_f32<nt, M2L_RT32><<<dim3((unsigned)T.n_m2l_tiles), 256, 0, s>>>(                                   \
-          T.m2l_tile_group.p, T.m2l_tile_row.p, T.m2l_group_off.p, T.m2l_group_end.p, T.far_order.p,           \
-          T.far_ts.p, T.t_m2l32, reinterpret_cast<const float *>(M), reinterpret_cast<float *>(m2l));          \
+      k_m2l_f32<nt, M2L_RT32><<<dim3((unsigned)ML.ntiles), 256, 0, s>>>(                                       \
+          ML.tile_group.p, ML.tile_row.p, ML.group_off.p, ML.group_end.p, ML.order.p, T.far_ts.p, T.t_m2l32,  \
+          reinterpret_cast<const float *>(M), reinterpret_cast<float *>(m2l));                                 \
     break;
       switch (NT) {
         M2L_CASE(1)
@@ -926,7 +930,7 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
       const bool leaf = (l == L);
       const size_t shm2 = (size_t)(ps + 64 * VecT<R>::W) * sizeof(R);
       k_downward<R><<<T.ncell[l], 64, shm2, s>>>(p, ps, T.coff[l], T.ncell[l], l > 2 ? 1 : 0, T.cparent.p, T.ckey.p,
-                                                 Sl, T.far_ptr.p, T.far_pos.p, m2l, Lx, leaf ? 1 : 0, R(1.0 / sL),
+                                                 Sl, T.far_ptr.p, ML.pos.p, m2l, Lx, leaf ? 1 : 0, R(1.0 / sL),
                                                  E);
       LAUNCH_OK();
     }

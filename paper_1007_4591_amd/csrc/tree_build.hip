@@ -522,6 +522,36 @@ __global__ void k_tile_list(const int32_t *__restrict__ gbeg, const int32_t *__r
   }
 }
 
+// keep a sorted M2L pair if its source cell has sources and its target cell
+// targets of the list's kinds (0 panels->panels, 1 charges->panels,
+// 2 panels->charges)
+__global__ void k_combo_flags(const int32_t *__restrict__ order, const int2 *__restrict__ ts,
+                              const int4 *__restrict__ crange, int64_t n, int combo, int32_t *__restrict__ flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int2 p = ts[order[i]];
+  const int4 rt = crange[p.x], rs = crange[p.y];
+  const bool tp = rt.y > rt.x, tq = rt.w > rt.z, sp = rs.y > rs.x, sq = rs.w > rs.z;
+  bool keep = combo == 0 ? (sp && tp) : (combo == 1 ? (sq && tp) : (sp && tq));
+  flag[i] = keep ? 1 : 0;
+}
+
+__global__ void k_combo_compact(const int32_t *__restrict__ order, const uint32_t *__restrict__ key,
+                                const int32_t *__restrict__ flag, const int32_t *__restrict__ pos, int64_t n,
+                                int32_t *__restrict__ order_k, uint32_t *__restrict__ key_k,
+                                int32_t *__restrict__ pos_k) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t pair = order[i];
+  if (flag[i]) {
+    order_k[pos[i]] = pair;
+    key_k[pos[i]] = key[i];
+    pos_k[pair] = pos[i];
+  } else {
+    pos_k[pair] = -1;
+  }
+}
+
 __global__ void k_far_ptr(const int32_t *__restrict__ cnt_scan, int32_t C, int64_t cl, int64_t foff,
                           int32_t *__restrict__ far_ptr) {
   int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -988,58 +1018,71 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     HIP_OK(hipStreamSynchronize(s));
   }
 
-  // group M2L pairs by translation offset (all levels together: the scaled
-  // operator depends on the offset only)
-  T.n_m2l_groups = 0;
-  T.n_m2l_tiles = 0;
+  // M2L pairs sorted by translation offset (all levels together: the scaled
+  // operator depends on the offset only), then one filtered list per
+  // (source kind, target kind)
   if (T.nfar > 0) {
     const int64_t nf = T.nfar;
     DBuf<uint32_t> key;
+    DBuf<int32_t> order;
     key.alloc(nf);
-    T.far_order.alloc(nf);
+    order.alloc(nf);
     err.zero(s);
-    k_offset_keys<<<cdiv(nf, TB), TB, 0, s>>>(T.far_ts.p, nf, T.cxyz.p, offid.p, T.tab->R, key.p, T.far_order.p,
-                                              err.p);
+    k_offset_keys<<<cdiv(nf, TB), TB, 0, s>>>(T.far_ts.p, nf, T.cxyz.p, offid.p, T.tab->R, key.p, order.p, err.p);
     LAUNCH_OK();
     if (read_err(err, s) & 8) BF_THROW(BEMFMM_EDEVICE, "tree build: M2L offset outside the operator table");
     int nbits = 1;
     while ((1 << nbits) < T.tab->noff()) ++nbits;
-    radix_sort_u32(key.p, T.far_order.p, nf, nbits, s);
-    DBuf<int32_t> flag, pos, gbeg;
+    radix_sort_u32(key.p, order.p, nf, nbits, s);
+    DBuf<int32_t> flag, pos;
+    DBuf<uint32_t> ckeyc;
     flag.alloc(nf);
     pos.alloc(nf);
-    k_group_flags<<<cdiv(nf, TB), TB, 0, s>>>(key.p, nf, flag.p);
-    LAUNCH_OK();
-    int32_t G = 0;
-    exclusive_scan_i32(flag.p, pos.p, nf, s, &G);
-    T.m2l_group_off.alloc(G);
-    T.m2l_group_end.alloc(G);
-    gbeg.alloc(G);
-    k_group_make<<<cdiv(nf, TB), TB, 0, s>>>(key.p, nf, flag.p, pos.p, T.m2l_group_off.p, gbeg.p,
-                                             T.m2l_group_end.p);
-    LAUNCH_OK();
-    for (int pass = 0; pass < 2; ++pass) {
-      const int ROWS = pass == 0 ? M2L_ROWS32 : M2L_ROWS64;
-      DBuf<int32_t> ntile, tpos;
-      ntile.alloc(G + 1);
-      tpos.alloc(G + 1);
-      k_group_tiles<<<cdiv(G, TB), TB, 0, s>>>(gbeg.p, T.m2l_group_end.p, G, ROWS, ntile.p);
+    ckeyc.alloc(nf);
+    for (int combo = 0; combo < 3; ++combo) {
+      Tree::M2LList &ML = T.m2l[combo];
+      k_combo_flags<<<cdiv(nf, TB), TB, 0, s>>>(order.p, T.far_ts.p, T.crange.p, nf, combo, flag.p);
       LAUNCH_OK();
-      HIP_OK(hipMemsetAsync(ntile.p + G, 0, 4, s));
-      int32_t ntiles = 0;
-      exclusive_scan_i32(ntile.p, tpos.p, G + 1, s, &ntiles);
-      DBuf<int32_t> &tg = pass == 0 ? T.m2l_tile_group : T.m2l_tile_group64;
-      DBuf<int32_t> &tr = pass == 0 ? T.m2l_tile_row : T.m2l_tile_row64;
-      tg.alloc(ntiles);
-      tr.alloc(ntiles);
-      k_tile_list<<<cdiv(G, TB), TB, 0, s>>>(gbeg.p, T.m2l_group_end.p, G, ROWS, tpos.p, tg.p, tr.p);
+      int32_t nk = 0;
+      exclusive_scan_i32(flag.p, pos.p, nf, s, &nk);
+      ML.n = nk;
+      ML.order.alloc(std::max<int32_t>(nk, 1));
+      ML.pos.alloc(nf);
+      k_combo_compact<<<cdiv(nf, TB), TB, 0, s>>>(order.p, key.p, flag.p, pos.p, nf, ML.order.p, ckeyc.p, ML.pos.p);
       LAUNCH_OK();
-      (pass == 0 ? T.n_m2l_tiles : T.n_m2l_tiles64) = ntiles;
+      if (nk == 0) continue;
+      DBuf<int32_t> gflag, gpos, gbeg;
+      gflag.alloc(nk);
+      gpos.alloc(nk);
+      k_group_flags<<<cdiv(nk, TB), TB, 0, s>>>(ckeyc.p, nk, gflag.p);
+      LAUNCH_OK();
+      int32_t G = 0;
+      exclusive_scan_i32(gflag.p, gpos.p, nk, s, &G);
+      ML.group_off.alloc(G);
+      ML.group_end.alloc(G);
+      gbeg.alloc(G);
+      k_group_make<<<cdiv(nk, TB), TB, 0, s>>>(ckeyc.p, nk, gflag.p, gpos.p, ML.group_off.p, gbeg.p, ML.group_end.p);
+      LAUNCH_OK();
+      ML.ngroups = G;
+      for (int pass = 0; pass < 2; ++pass) {
+        const int ROWS = pass == 0 ? M2L_ROWS32 : M2L_ROWS64;
+        DBuf<int32_t> ntile, tpos;
+        ntile.alloc(G + 1);
+        tpos.alloc(G + 1);
+        k_group_tiles<<<cdiv(G, TB), TB, 0, s>>>(gbeg.p, ML.group_end.p, G, ROWS, ntile.p);
+        LAUNCH_OK();
+        HIP_OK(hipMemsetAsync(ntile.p + G, 0, 4, s));
+        int32_t ntiles = 0;
+        exclusive_scan_i32(ntile.p, tpos.p, G + 1, s, &ntiles);
+        DBuf<int32_t> &tg = pass == 0 ? ML.tile_group : ML.tile_group64;
+        DBuf<int32_t> &tr = pass == 0 ? ML.tile_row : ML.tile_row64;
+        tg.alloc(ntiles);
+        tr.alloc(ntiles);
+        k_tile_list<<<cdiv(G, TB), TB, 0, s>>>(gbeg.p, ML.group_end.p, G, ROWS, tpos.p, tg.p, tr.p);
+        LAUNCH_OK();
+        (pass == 0 ? ML.ntiles : ML.ntiles64) = ntiles;
+      }
     }
-    T.n_m2l_groups = G;
-    T.far_pos.alloc(nf);
-    k_inverse_perm<<<cdiv(nf, TB), TB, 0, s>>>(T.far_order.p, nf, T.far_pos.p);
-    LAUNCH_OK();
   }
 
   // leaf membership, inverse permutations, sorted point data
