@@ -134,7 +134,7 @@ def main():
     p2p_ms = stages["p2p"][0] / max(stages["p2p"][1], 1)
     m2l_ms = stages["m2l"][0] / max(stages["m2l"][1], 1)
     p2p_flops = info["p2p_pairs_panels"] * P2P_FLOPS_PER_PAIR
-    m2l_flops = info["n_far_pairs"] * M2L_FLOPS_PER_PAIR
+    m2l_flops = info["n_m2l_panel_pairs"] * M2L_FLOPS_PER_PAIR
     roof_p2p = {"bound": "alu", "kernel": "k_p2p (P2P + L2P, FP32)", "achieved": p2p_flops / (p2p_ms / 1e3) / 1e12,
                 "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s", "avg_ms": p2p_ms, "traffic": None}
     roof_p2p["frac"] = roof_p2p["achieved"] / roof_p2p["peak"]
@@ -192,7 +192,7 @@ def main():
         "solve_to_1e-6": solves,
         "energies": {"dG_kcal_mol": dG, "bibee_cfa_kcal_mol": bib},
         "stages_ms_per_matvec_fp32": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
-        "tree": {k: info[k] for k in ("leaf_level", "n_cells", "n_leaves", "n_near_pairs", "n_far_pairs",
+        "tree": {k: info[k] for k in ("leaf_level", "n_cells", "n_leaves", "n_near_pairs", "n_far_pairs", "n_m2l_panel_pairs",
                                       "n_offsets", "p2p_pairs_panels")},
         "roofline": roofline,
         "roofline_other": roof_m2l if roofline is roof_p2p else roof_p2p,

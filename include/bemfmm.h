@@ -105,6 +105,7 @@ typedef struct {
   int64_t n_leaves;
   int64_t n_near_pairs;     /* leaf-level near (P2P) cell pairs */
   int64_t n_far_pairs;      /* M2L cell pairs, all levels */
+  int64_t n_m2l_panel_pairs;/* M2L pairs whose cells both hold panels (the A, A^T work) */
   int64_t n_offsets;        /* distinct M2L translation offsets */
   int64_t p2p_pairs_panels; /* sum over near cell pairs of n_t * n_s (panels -> panels) */
   double lo[3];             /* root cube corner */

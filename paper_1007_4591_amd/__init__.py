@@ -51,7 +51,8 @@ class _SolveInfo(ctypes.Structure):
 class _TreeInfo(ctypes.Structure):
     _fields_ = [("n_panels", ctypes.c_int64), ("n_charges", ctypes.c_int64), ("leaf_level", ctypes.c_int),
                 ("n_cells", ctypes.c_int64), ("n_leaves", ctypes.c_int64), ("n_near_pairs", ctypes.c_int64),
-                ("n_far_pairs", ctypes.c_int64), ("n_offsets", ctypes.c_int64),
+                ("n_far_pairs", ctypes.c_int64), ("n_m2l_panel_pairs", ctypes.c_int64),
+                ("n_offsets", ctypes.c_int64),
                 ("p2p_pairs_panels", ctypes.c_int64), ("lo", ctypes.c_double * 3), ("side", ctypes.c_double)]
 
 

@@ -114,6 +114,7 @@ int bemfmm_tree_get_info(const bemfmm_tree *tree, bemfmm_tree_info *info) {
     I.n_leaves = T->ncell[T->L];
     I.n_near_pairs = T->n_near_leaf;
     I.n_far_pairs = T->nfar;
+    I.n_m2l_panel_pairs = T->m2l[0].n;
     I.n_offsets = T->tab ? T->tab->noff() : 0;
     I.p2p_pairs_panels = T->p2p_pairs_pp;
     for (int d = 0; d < 3; ++d) I.lo[d] = T->lo[d];

@@ -622,13 +622,34 @@ __global__ void __launch_bounds__(64) k_p2p(P2PArgs a) {
     const R ux = tx + R(txi - sxi) * sL, uy = ty + R(tyi - syi) * sL, uz = tz + R(tzi - szi) * sL;
     R lp = R(0), lx = R(0), ly = R(0), lz = R(0);
     const bool self = (SRC != SRC_CHARGE_MONO) && (TGT == TGT_PANEL) && (sl == leaf);
-    if (active) {
+    if (G == 1) {
+      // one lane group: the source index is uniform across the wave, so the
+      // source records come through the scalar cache
+      if (self) {
+        for (int j = sb; j < se; ++j) {
+          const R4 s4 = spos[j];
+          const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
+          const R r2 = dx * dx + dy * dy + dz * dz;
+          const R ri = (j == ti) ? R(0) : rsq(r2);  // K'_ii = 0: the self panel is skipped by index
+          pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
+        }
+      } else {
+#pragma unroll 4
+        for (int j = sb; j < se; ++j) {
+          const R4 s4 = spos[j];
+          const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
+          const R r2 = dx * dx + dy * dy + dz * dz;
+          const R ri = rsq(r2);
+          pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
+        }
+      }
+    } else if (active) {
       if (self) {
         for (int j = sb + g; j < se; j += G) {
           const R4 s4 = spos[j];
           const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
           const R r2 = dx * dx + dy * dy + dz * dz;
-          const R ri = (j == ti) ? R(0) : rsq(r2);  // K'_ii = 0: the self panel is skipped by index
+          const R ri = (j == ti) ? R(0) : rsq(r2);
           pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
         }
       } else {
