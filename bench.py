@@ -128,14 +128,15 @@ def main():
     nprof = 5
     for _ in range(nprof):
         B.fmm_matvec(tree, B.OP_A, B.FP32, xv, yv)
-    stages = {s: B.profile_get(tree, s) for s in ("p2m", "m2m", "m2l", "l2l", "p2p", "other")}
+    stages = {s: B.profile_get(tree, s) for s in ("p2m", "m2m", "m2l", "l2l", "p2p", "l2p", "other")}
     B.profile(tree, False, True)
     info = tree.info
     p2p_ms = stages["p2p"][0] / max(stages["p2p"][1], 1)
     m2l_ms = stages["m2l"][0] / max(stages["m2l"][1], 1)
     p2p_flops = info["p2p_pairs_panels"] * P2P_FLOPS_PER_PAIR
     m2l_flops = info["n_m2l_panel_pairs"] * M2L_FLOPS_PER_PAIR
-    roof_p2p = {"bound": "alu", "kernel": "k_p2p (P2P + L2P, FP32)", "achieved": p2p_flops / (p2p_ms / 1e3) / 1e12,
+    roof_p2p = {"bound": "alu", "kernel": "k_p2p_near (P2P near field, FP32, side stream)",
+                "achieved": p2p_flops / (p2p_ms / 1e3) / 1e12,
                 "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s", "avg_ms": p2p_ms, "traffic": None}
     roof_p2p["frac"] = roof_p2p["achieved"] / roof_p2p["peak"]
     roof_m2l = {"bound": "mfma", "kernel": "k_m2l_f32 (M2L, FP32 MFMA)", "achieved": m2l_flops / (m2l_ms / 1e3) / 1e12,

@@ -15,8 +15,12 @@ void set_error(const std::string &msg) { g_err = msg; }
 
 Tree::~Tree() {
   fmm_free(*this);
-  if (ev_init)
+  if (ev_init) {
     for (auto &e : ev) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(ev_fork);
+    (void)hipEventDestroy(ev_join);
+    (void)hipStreamDestroy(side_stream);
+  }
   magic = 0;
 }
 
@@ -232,7 +236,7 @@ int bemfmm_profile(bemfmm_tree *tree, int enable, int reset) {
     Tree *T = check_tree(tree);
     T->prof = enable != 0;
     if (reset)
-      for (int i = 0; i < 6; ++i) {
+      for (int i = 0; i < 7; ++i) {
         T->prof_ms[i] = 0;
         T->prof_cnt[i] = 0;
       }
@@ -242,9 +246,9 @@ int bemfmm_profile(bemfmm_tree *tree, int enable, int reset) {
 int bemfmm_profile_get(bemfmm_tree *tree, const char *stage, double *ms_host, int64_t *count_host) {
   return guard([&] {
     Tree *T = check_tree(tree);
-    static const char *names[6] = {"p2m", "m2m", "m2l", "l2l", "p2p", "other"};
+    static const char *names[7] = {"p2m", "m2m", "m2l", "l2l", "p2p", "other", "l2p"};
     int k = -1;
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 7; ++i)
       if (stage && std::strcmp(stage, names[i]) == 0) k = i;
     need(k >= 0, "unknown stage");
     if (ms_host) *ms_host = T->prof_ms[k];

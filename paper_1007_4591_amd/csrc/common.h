@@ -204,11 +204,15 @@ struct Tree {
     return b->p;
   }
 
-  // stage profiling
+  // second stream for the near field (default priority) and its fork/join
+  // events; stage profiling events
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool prof = false;
-  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
-  int64_t prof_cnt[6] = {0, 0, 0, 0, 0, 0};
-  hipEvent_t ev[12] = {};
+  double prof_ms[7] = {0, 0, 0, 0, 0, 0, 0};
+  int64_t prof_cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+  bool prof_pending[7] = {false, false, false, false, false, false, false};
+  hipEvent_t ev[14] = {};
   bool ev_init = false;
 
   int last_op32 = -1, last_op64 = -1;
@@ -264,7 +268,7 @@ void adjoint(Tree &T, const double *q, const double *x, double tol, int maxit, i
 double dot_d(Tree &T, const double *a, const double *b, int64_t n, hipStream_t s);
 
 // profiling helpers (fmm.hip)
-enum Stage { ST_P2M = 0, ST_M2M = 1, ST_M2L = 2, ST_L2L = 3, ST_P2P = 4, ST_OTHER = 5 };
+enum Stage { ST_P2M = 0, ST_M2M = 1, ST_M2L = 2, ST_L2L = 3, ST_P2P = 4, ST_OTHER = 5, ST_L2P = 6 };
 void prof_begin(Tree &T, int stage, hipStream_t s);
 void prof_end(Tree &T, int stage, hipStream_t s);
 

@@ -30,6 +30,7 @@ struct PrecBufs {
   DBuf<char> m2l_out;           // real [nfar * ps]
   DBuf<char> E;                 // real [nleaf * 4 * ps]
   DBuf<double> dbg_near, dbg_far;  // sorted-order raw fields (debug)
+  DBuf<double> near_out;           // near field per target (sorted order)
   int last_tgt = 0;
   bool have = false;
 };
@@ -579,18 +580,20 @@ struct P2PArgs {
   int accumulate;
   double *y;
   double *dbg_near, *dbg_far;  // sorted order, may be NULL
+  double *near_out;            // near field per target, sorted order ([n] or [4n])
 };
 
-// One wave per chunk of up to 64 targets of one leaf.  A chunk of n targets
-// uses G = 64 / n lane groups: lane l works on target l % n and on every
-// G-th source of each near leaf (starting at l / n), so small leaves still
-// fill the wave.  Each lane sums one source leaf in plain arithmetic, adds
-// the leaf total to a compensated (Kahan) accumulator, and the G partial
-// results are added in group order through LDS.  The far field (L2P from
-// the leaf's evaluation coefficients) and the operator's combination are
-// applied once per target.
+// Near field (P2P).  One wave per chunk of up to 64 targets of one leaf.  A
+// chunk of n targets uses G = 64 / n lane groups: lane l works on target
+// l % n and on every G-th source of each near leaf (starting at l / n), so
+// small leaves still fill the wave; with one group the source index is
+// uniform and the records come through the scalar cache.  Each lane sums
+// one source leaf in plain arithmetic, adds the leaf total to a compensated
+// (Kahan) accumulator, and the G partial results are added in group order
+// through LDS.  The per-target result (potential, normal derivative, or
+// potential and -gradient) goes to near_out in sorted order, in FP64.
 template <class R, int SRC, int TGT, int OUT>
-__global__ void __launch_bounds__(64) k_p2p(P2PArgs a) {
+__global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
   using R4 = typename V4<R>::T;
   __shared__ R red[4][64];
   const int4 ch = a.chunks[blockIdx.x];  // (leaf, first target, count, groups)
@@ -697,12 +700,36 @@ __global__ void __launch_bounds__(64) k_p2p(P2PArgs a) {
     }
   }
   if (g != 0) return;
-  // ---- far field: L2P from the leaf's evaluation coefficients
+  if (OUT == OUT_POT) {
+    a.near_out[ti] = (double)sp;
+  } else if (OUT == OUT_NGRAD) {
+    const R4 nn = reinterpret_cast<const R4 *>(a.tgt_nrm)[ti];
+    a.near_out[ti] = -((double)nn.x * sx + (double)nn.y * sy + (double)nn.z * sz);
+  } else {
+    a.near_out[4 * (size_t)ti] = (double)sp;
+    a.near_out[4 * (size_t)ti + 1] = -(double)sx;
+    a.near_out[4 * (size_t)ti + 2] = -(double)sy;
+    a.near_out[4 * (size_t)ti + 3] = -(double)sz;
+  }
+}
+
+// Far field (L2P from the leaf's evaluation coefficients, read through the
+// scalar cache) plus the near field, combined into the operator's output in
+// the caller's order: y = alpha x + beta (area) field.
+template <class R, int TGT, int OUT>
+__global__ void __launch_bounds__(64) k_l2p_combine(P2PArgs a) {
+  using R4 = typename V4<R>::T;
+  const int4 ch = a.chunks[blockIdx.x];
+  const int leaf = ch.x, count = ch.z;
+  const int tl = threadIdx.x;
+  if (tl >= count) return;
+  const int ti = ch.y + tl;
+  const R4 tp = reinterpret_cast<const R4 *>(a.tgt_pos)[ti];
   const R *E = reinterpret_cast<const R *>(a.E) + (size_t)leaf * 4 * a.ps;
   const R inv_s = R(1.0 / a.sL);
   R fp = R(0), fgx = R(0), fgy = R(0), fgz = R(0);
   {
-    const R x = tx * inv_s, y = ty * inv_s, z = tz * inv_s;
+    const R x = tp.x * inv_s, y = tp.y * inv_s, z = tp.z * inv_s;
     const int p = a.p;
     regular_harmonics<R>(p, x, y, z, [&](int n, int m, R re, R im) {
       const int kr = idx_re(n, m);
@@ -723,28 +750,25 @@ __global__ void __launch_bounds__(64) k_p2p(P2PArgs a) {
       }
     });
   }
-  // the near sums hold -grad (sum w d / r^3 for monopoles, and the dipole
-  // terms with the same sign): grad = -(sx, sy, sz)
   const int64_t u = a.tperm[ti];
-  double near_v, far_v;
-  double res[4];
+  double res[4], near_v, far_v;
   int nres = 1;
   if (OUT == OUT_POT) {
-    near_v = (double)sp;
+    near_v = a.near_out[ti];
     far_v = (double)fp;
     res[0] = near_v + far_v;
   } else if (OUT == OUT_NGRAD) {
     const R4 nn = reinterpret_cast<const R4 *>(a.tgt_nrm)[ti];
-    near_v = -((double)nn.x * sx + (double)nn.y * sy + (double)nn.z * sz);
+    near_v = a.near_out[ti];
     far_v = (double)nn.x * fgx + (double)nn.y * fgy + (double)nn.z * fgz;
     res[0] = near_v + far_v;
   } else {
-    near_v = (double)sp;
+    near_v = a.near_out[4 * (size_t)ti];
     far_v = (double)fp;
     res[0] = near_v + far_v;
-    res[1] = -(double)sx + (double)fgx;
-    res[2] = -(double)sy + (double)fgy;
-    res[3] = -(double)sz + (double)fgz;
+    res[1] = a.near_out[4 * (size_t)ti + 1] + (double)fgx;
+    res[2] = a.near_out[4 * (size_t)ti + 2] + (double)fgy;
+    res[3] = a.near_out[4 * (size_t)ti + 3] + (double)fgz;
     nres = 4;
   }
   if (a.dbg_near) {
@@ -799,6 +823,9 @@ void set_rec_constants() {
 
 // ---------------------------------------------------------------- driver
 
+// Stage timing: events are recorded on the stream that runs the stage and
+// read after the product has finished, so profiling does not serialise the
+// two streams.
 void prof_begin(Tree &T, int stage, hipStream_t s) {
   if (!T.prof) return;
   HIP_OK(hipEventRecord(T.ev[2 * stage], s));
@@ -807,11 +834,20 @@ void prof_begin(Tree &T, int stage, hipStream_t s) {
 void prof_end(Tree &T, int stage, hipStream_t s) {
   if (!T.prof) return;
   HIP_OK(hipEventRecord(T.ev[2 * stage + 1], s));
-  HIP_OK(hipEventSynchronize(T.ev[2 * stage + 1]));
-  float ms = 0.f;
-  HIP_OK(hipEventElapsedTime(&ms, T.ev[2 * stage], T.ev[2 * stage + 1]));
-  T.prof_ms[stage] += ms;
-  T.prof_cnt[stage] += 1;
+  T.prof_pending[stage] = true;
+}
+
+static void prof_collect(Tree &T) {
+  if (!T.prof) return;
+  for (int st = 0; st < 6; ++st) {
+    if (!T.prof_pending[st]) continue;
+    HIP_OK(hipEventSynchronize(T.ev[2 * st + 1]));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, T.ev[2 * st], T.ev[2 * st + 1]));
+    T.prof_ms[st] += ms;
+    T.prof_cnt[st] += 1;
+    T.prof_pending[st] = false;
+  }
 }
 
 static PrecBufs &bufs(Tree &T, int prec, hipStream_t s) {
@@ -828,6 +864,7 @@ static PrecBufs &bufs(Tree &T, int prec, hipStream_t s) {
     pb->E.alloc((size_t)T.ncell[T.L] * 4 * T.ps * rs);
     pb->dbg_near.alloc(npts);
     pb->dbg_far.alloc(npts);
+    pb->near_out.alloc(4 * npts);
     pb->M.zero(s);
     pb->L.zero(s);
     pb->E.zero(s);
@@ -897,6 +934,60 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     LAUNCH_OK();
   }
   prof_end(T, ST_OTHER, s);
+  HIP_OK(hipEventRecord(T.ev_fork, s));
+  // near field on the side stream, concurrent with the multipole passes
+  // above (VALU-bound P2P next to MFMA-bound M2L); joined before L2P
+  P2PArgs a{};
+  a.p = p;
+  a.ps = ps;
+  const bool tgt_ch = rq.tgt == TGT_CHARGE;
+  a.chunks = tgt_ch ? T.chunk_q.p : T.chunk_p.p;
+  const int64_t nchunks = tgt_ch ? T.nchunk_q : T.nchunk_p;
+  a.leaf_range = T.crange.p + T.coff[L];
+  a.leaf_xyz = T.cxyz.p + T.coff[L];
+  a.near_ptr = T.near_ptr.p + T.near_ptr_off[L];
+  a.near_idx = T.near_idx.p + T.near_off[L];
+  a.tgt_pos = tgt_ch ? (f64 ? (const void *)T.q64pos.p : (const void *)T.q32pos.p)
+                     : (f64 ? (const void *)T.p64pos.p : (const void *)T.p32pos.p);
+  a.tgt_nrm = f64 ? (const void *)T.p64nrm.p : (const void *)T.p32nrm.p;
+  a.src_pos = spos;
+  a.src_dip = sdip;
+  a.E = E;
+  a.tperm = tgt_ch ? T.qperm.p : T.pperm.p;
+  a.sL = sL;
+  a.xin = rq.xin;
+  a.alpha = rq.alpha;
+  a.beta = rq.beta / (4.0 * PI);
+  a.area_scale = rq.area_scale ? 1 : 0;
+  a.accumulate = rq.accumulate ? 1 : 0;
+  a.y = rq.y;
+  a.dbg_near = B.dbg_near.p;
+  a.dbg_far = B.dbg_far.p;
+  a.near_out = B.near_out.p;
+  B.last_tgt = rq.tgt;
+  if (nchunks > 0) {
+    HIP_OK(hipStreamWaitEvent(T.side_stream, T.ev_fork, 0));
+    const hipStream_t ss = T.side_stream;
+    prof_begin(T, ST_P2P, ss);
+#define P2P_CALL(S, Tg, O) k_p2p_near<R, S, Tg, O><<<nchunks, 64, 0, ss>>>(a)
+    if (!tgt_ch) {
+      if (rq.src == SRC_PANEL_MONO && rq.out == OUT_NGRAD) P2P_CALL(SRC_PANEL_MONO, TGT_PANEL, OUT_NGRAD);
+      else if (rq.src == SRC_PANEL_DIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_DIP, TGT_PANEL, OUT_POT);
+      else if (rq.src == SRC_CHARGE_MONO && rq.out == OUT_NGRAD) P2P_CALL(SRC_CHARGE_MONO, TGT_PANEL, OUT_NGRAD);
+      else if (rq.src == SRC_CHARGE_MONO && rq.out == OUT_POT) P2P_CALL(SRC_CHARGE_MONO, TGT_PANEL, OUT_POT);
+      else BF_THROW(BEMFMM_EINVAL, "unsupported FMM request (panel targets)");
+    } else {
+      if (rq.src == SRC_PANEL_MONO && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_MONO, TGT_CHARGE, OUT_POT);
+      else if (rq.src == SRC_PANEL_DIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_DIP, TGT_CHARGE, OUT_POT);
+      else if (rq.src == SRC_PANEL_MONODIP && rq.out == OUT_POTGRAD) P2P_CALL(SRC_PANEL_MONODIP, TGT_CHARGE, OUT_POTGRAD);
+      else if (rq.src == SRC_PANEL_MONODIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_MONODIP, TGT_CHARGE, OUT_POT);
+      else BF_THROW(BEMFMM_EINVAL, "unsupported FMM request (charge targets)");
+    }
+#undef P2P_CALL
+    LAUNCH_OK();
+    prof_end(T, ST_P2P, ss);
+    HIP_OK(hipEventRecord(T.ev_join, ss));
+  }
 
   const int combo = src_charges ? 1 : (rq.tgt == TGT_CHARGE ? 2 : 0);
   const Tree::M2LList &ML = T.m2l[combo];
@@ -960,63 +1051,33 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     B.E.zero(s);
   }
 
-  // P2P + L2P + the operator's combination
-  prof_begin(T, ST_P2P, s);
-  P2PArgs a{};
-  a.p = p;
-  a.ps = ps;
-  const bool tgt_ch = rq.tgt == TGT_CHARGE;
-  a.chunks = tgt_ch ? T.chunk_q.p : T.chunk_p.p;
-  const int64_t nchunks = tgt_ch ? T.nchunk_q : T.nchunk_p;
-  a.leaf_range = T.crange.p + T.coff[L];
-  a.leaf_xyz = T.cxyz.p + T.coff[L];
-  a.near_ptr = T.near_ptr.p + T.near_ptr_off[L];
-  a.near_idx = T.near_idx.p + T.near_off[L];
-  a.tgt_pos = tgt_ch ? (f64 ? (const void *)T.q64pos.p : (const void *)T.q32pos.p)
-                     : (f64 ? (const void *)T.p64pos.p : (const void *)T.p32pos.p);
-  a.tgt_nrm = f64 ? (const void *)T.p64nrm.p : (const void *)T.p32nrm.p;
-  a.src_pos = spos;
-  a.src_dip = sdip;
-  a.E = E;
-  a.tperm = tgt_ch ? T.qperm.p : T.pperm.p;
-  a.sL = sL;
-  a.xin = rq.xin;
-  a.alpha = rq.alpha;
-  a.beta = rq.beta / (4.0 * PI);
-  a.area_scale = rq.area_scale ? 1 : 0;
-  a.accumulate = rq.accumulate ? 1 : 0;
-  a.y = rq.y;
-  a.dbg_near = B.dbg_near.p;
-  a.dbg_far = B.dbg_far.p;
-  B.last_tgt = rq.tgt;
+  // far field + near field -> output, after the join
   if (nchunks > 0) {
-#define P2P_CALL(S, Tg, O) k_p2p<R, S, Tg, O><<<nchunks, 64, 0, s>>>(a)
+    HIP_OK(hipStreamWaitEvent(s, T.ev_join, 0));
+    prof_begin(T, ST_L2P, s);
     if (!tgt_ch) {
-      if (rq.src == SRC_PANEL_MONO && rq.out == OUT_NGRAD) P2P_CALL(SRC_PANEL_MONO, TGT_PANEL, OUT_NGRAD);
-      else if (rq.src == SRC_PANEL_DIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_DIP, TGT_PANEL, OUT_POT);
-      else if (rq.src == SRC_CHARGE_MONO && rq.out == OUT_NGRAD) P2P_CALL(SRC_CHARGE_MONO, TGT_PANEL, OUT_NGRAD);
-      else if (rq.src == SRC_CHARGE_MONO && rq.out == OUT_POT) P2P_CALL(SRC_CHARGE_MONO, TGT_PANEL, OUT_POT);
-      else BF_THROW(BEMFMM_EINVAL, "unsupported FMM request (panel targets)");
+      if (rq.out == OUT_NGRAD) k_l2p_combine<R, TGT_PANEL, OUT_NGRAD><<<nchunks, 64, 0, s>>>(a);
+      else k_l2p_combine<R, TGT_PANEL, OUT_POT><<<nchunks, 64, 0, s>>>(a);
     } else {
-      if (rq.src == SRC_PANEL_MONO && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_MONO, TGT_CHARGE, OUT_POT);
-      else if (rq.src == SRC_PANEL_DIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_DIP, TGT_CHARGE, OUT_POT);
-      else if (rq.src == SRC_PANEL_MONODIP && rq.out == OUT_POTGRAD) P2P_CALL(SRC_PANEL_MONODIP, TGT_CHARGE, OUT_POTGRAD);
-      else if (rq.src == SRC_PANEL_MONODIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_MONODIP, TGT_CHARGE, OUT_POT);
-      else BF_THROW(BEMFMM_EINVAL, "unsupported FMM request (charge targets)");
+      if (rq.out == OUT_POTGRAD) k_l2p_combine<R, TGT_CHARGE, OUT_POTGRAD><<<nchunks, 64, 0, s>>>(a);
+      else k_l2p_combine<R, TGT_CHARGE, OUT_POT><<<nchunks, 64, 0, s>>>(a);
     }
-#undef P2P_CALL
     LAUNCH_OK();
+    prof_end(T, ST_L2P, s);
   }
-  prof_end(T, ST_P2P, s);
   B.have = true;
+  prof_collect(T);
 }
 
 void fmm_apply(Tree &T, int precision, const FmmRequest &rq, hipStream_t s) {
   const int prec = (precision == BEMFMM_FP64) ? BEMFMM_FP64 : BEMFMM_FP32;
   if (rq.tgt == TGT_CHARGE && T.Q == 0) return;
   PrecBufs &B = bufs(T, prec, s);
-  if (T.prof && !T.ev_init) {
+  if (!T.ev_init) {
     for (auto &e : T.ev) HIP_OK(hipEventCreate(&e));
+    HIP_OK(hipEventCreateWithFlags(&T.ev_fork, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&T.ev_join, hipEventDisableTiming));
+    HIP_OK(hipStreamCreateWithFlags(&T.side_stream, hipStreamNonBlocking));  // default priority
     T.ev_init = true;
   }
   if (prec == BEMFMM_FP64)
