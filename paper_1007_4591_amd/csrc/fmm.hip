@@ -416,16 +416,35 @@ __global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int6
   for (int w = 0; w < W; ++w) s[w] = comp[w] = R(0);
   const int b = far_ptr[c], e = far_ptr[c + 1];
   if (act) {
-    for (int q = b + grp; q < e; q += groups) {
-      const int row = far_pos[q];
-      if (row < 0) continue;  // pair not in this product's list
-      const VT v = reinterpret_cast<const VT *>(m2l + (size_t)row * ps)[k4];
-      R x[W];
+    // four rows in flight per lane group, added in order
+    int q = b + grp;
+    for (; q + 3 * groups < e; q += 4 * groups) {
+      int rows[4];
+      VT v[4];
 #pragma unroll
-      for (int w = 0; w < W; ++w) x[w] = reinterpret_cast<const R *>(&v)[w];
+      for (int u = 0; u < 4; ++u) rows[u] = far_pos[q + u * groups];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (rows[u] >= 0) v[u] = reinterpret_cast<const VT *>(m2l + (size_t)rows[u] * ps)[k4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (rows[u] < 0) continue;  // pair not in this product's list
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const R y = reinterpret_cast<const R *>(&v[u])[w] - comp[w];
+          const R t = s[w] + y;
+          comp[w] = (t - s[w]) - y;
+          s[w] = t;
+        }
+      }
+    }
+    for (; q < e; q += groups) {
+      const int row = far_pos[q];
+      if (row < 0) continue;
+      const VT v = reinterpret_cast<const VT *>(m2l + (size_t)row * ps)[k4];
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        const R y = x[w] - comp[w];
+        const R y = reinterpret_cast<const R *>(&v)[w] - comp[w];
         const R t = s[w] + y;
         comp[w] = (t - s[w]) - y;
         s[w] = t;
@@ -839,7 +858,7 @@ void prof_end(Tree &T, int stage, hipStream_t s) {
 
 static void prof_collect(Tree &T) {
   if (!T.prof) return;
-  for (int st = 0; st < 6; ++st) {
+  for (int st = 0; st < 7; ++st) {
     if (!T.prof_pending[st]) continue;
     HIP_OK(hipEventSynchronize(T.ev[2 * st + 1]));
     float ms = 0.f;
@@ -934,9 +953,25 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     LAUNCH_OK();
   }
   prof_end(T, ST_OTHER, s);
+  const int combo = src_charges ? 1 : (rq.tgt == TGT_CHARGE ? 2 : 0);
+  const Tree::M2LList &ML = T.m2l[combo];
+  const bool far = (L >= 2) && T.nfar > 0;
+  if (far) {
+    prof_begin(T, ST_P2M, s);
+    launch_p2m<R>(T, B, rq.src, s);
+    prof_end(T, ST_P2M, s);
+    // M2M, levels L-1 .. 2
+    prof_begin(T, ST_M2M, s);
+    const R *Sm = f64 ? reinterpret_cast<const R *>(T.t_m2m64) : reinterpret_cast<const R *>(T.t_m2m32);
+    for (int l = L - 1; l >= 2; --l) {
+      k_m2m<R><<<T.ncell[l], 64, 0, s>>>(p * p, ps, T.coff[l], T.ncell[l], T.cchild.p, T.ckey.p, Sm, M);
+      LAUNCH_OK();
+    }
+    prof_end(T, ST_M2M, s);
+  }
+  // near field on the side stream, concurrent with M2L and the downward
+  // pass (VALU-bound P2P next to MFMA-bound M2L); joined before L2P
   HIP_OK(hipEventRecord(T.ev_fork, s));
-  // near field on the side stream, concurrent with the multipole passes
-  // above (VALU-bound P2P next to MFMA-bound M2L); joined before L2P
   P2PArgs a{};
   a.p = p;
   a.ps = ps;
@@ -989,21 +1024,7 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     HIP_OK(hipEventRecord(T.ev_join, ss));
   }
 
-  const int combo = src_charges ? 1 : (rq.tgt == TGT_CHARGE ? 2 : 0);
-  const Tree::M2LList &ML = T.m2l[combo];
-  const bool far = (L >= 2) && T.nfar > 0;
   if (far) {
-    prof_begin(T, ST_P2M, s);
-    launch_p2m<R>(T, B, rq.src, s);
-    prof_end(T, ST_P2M, s);
-    // M2M, levels L-1 .. 2
-    prof_begin(T, ST_M2M, s);
-    const R *Sm = f64 ? reinterpret_cast<const R *>(T.t_m2m64) : reinterpret_cast<const R *>(T.t_m2m32);
-    for (int l = L - 1; l >= 2; --l) {
-      k_m2m<R><<<T.ncell[l], 64, 0, s>>>(p * p, ps, T.coff[l], T.ncell[l], T.cchild.p, T.ckey.p, Sm, M);
-      LAUNCH_OK();
-    }
-    prof_end(T, ST_M2M, s);
     // M2L, every level in one launch
     prof_begin(T, ST_M2L, s);
     const int NT = ps / 16;
