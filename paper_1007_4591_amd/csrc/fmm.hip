@@ -953,24 +953,8 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     LAUNCH_OK();
   }
   prof_end(T, ST_OTHER, s);
-  const int combo = src_charges ? 1 : (rq.tgt == TGT_CHARGE ? 2 : 0);
-  const Tree::M2LList &ML = T.m2l[combo];
-  const bool far = (L >= 2) && T.nfar > 0;
-  if (far) {
-    prof_begin(T, ST_P2M, s);
-    launch_p2m<R>(T, B, rq.src, s);
-    prof_end(T, ST_P2M, s);
-    // M2M, levels L-1 .. 2
-    prof_begin(T, ST_M2M, s);
-    const R *Sm = f64 ? reinterpret_cast<const R *>(T.t_m2m64) : reinterpret_cast<const R *>(T.t_m2m32);
-    for (int l = L - 1; l >= 2; --l) {
-      k_m2m<R><<<T.ncell[l], 64, 0, s>>>(p * p, ps, T.coff[l], T.ncell[l], T.cchild.p, T.ckey.p, Sm, M);
-      LAUNCH_OK();
-    }
-    prof_end(T, ST_M2M, s);
-  }
-  // near field on the side stream, concurrent with M2L and the downward
-  // pass (VALU-bound P2P next to MFMA-bound M2L); joined before L2P
+  // near field on the side stream, concurrent with the multipole passes on
+  // the caller's stream; joined before L2P
   HIP_OK(hipEventRecord(T.ev_fork, s));
   P2PArgs a{};
   a.p = p;
@@ -1024,6 +1008,22 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     HIP_OK(hipEventRecord(T.ev_join, ss));
   }
 
+  const int combo = src_charges ? 1 : (rq.tgt == TGT_CHARGE ? 2 : 0);
+  const Tree::M2LList &ML = T.m2l[combo];
+  const bool far = (L >= 2) && T.nfar > 0;
+  if (far) {
+    prof_begin(T, ST_P2M, s);
+    launch_p2m<R>(T, B, rq.src, s);
+    prof_end(T, ST_P2M, s);
+    // M2M, levels L-1 .. 2
+    prof_begin(T, ST_M2M, s);
+    const R *Sm = f64 ? reinterpret_cast<const R *>(T.t_m2m64) : reinterpret_cast<const R *>(T.t_m2m32);
+    for (int l = L - 1; l >= 2; --l) {
+      k_m2m<R><<<T.ncell[l], 64, 0, s>>>(p * p, ps, T.coff[l], T.ncell[l], T.cchild.p, T.ckey.p, Sm, M);
+      LAUNCH_OK();
+    }
+    prof_end(T, ST_M2M, s);
+  }
   if (far) {
     // M2L, every level in one launch
     prof_begin(T, ST_M2L, s);
