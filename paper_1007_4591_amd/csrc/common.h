@@ -188,18 +188,6 @@ struct Tree {
   const float *t_m2m32 = nullptr, *t_l2l32 = nullptr;   // [8][ps in][ps out] (transposed)
   const double *t_m2m64 = nullptr, *t_l2l64 = nullptr;
 
-  // Symmetric panel-panel near field (A and A^T): every unordered pair of
-  // near leaves is evaluated once.  For the leaf-level near entry e = (t, s):
-  // sym_R[e] partial results per target of t (1, or the number of 64-target
-  // chunks of s when s drives the lanes), stored from sym_off[e]:
-  // near_part[sym_off[e] + r * |t| + (i - first panel of t)].
-  // Work items: (lane leaf, first target, count, loop leaf) and
-  // (forward entry, reverse entry or -1 for the self pair, chunk, 0).
-  DBuf<int32_t> sym_R, sym_off;
-  DBuf<int4> sym_item, sym_item2;
-  int64_t n_sym_items = 0, n_sym_slots = 0;
-  bool use_sym = true;
-
   // P2P work decomposition: (leaf, first sorted index, count, lane groups)
   // per chunk of at most 64 targets of one leaf
   DBuf<int4> chunk_p, chunk_q;
@@ -219,6 +207,7 @@ struct Tree {
   // second stream for the near field (default priority) and its fork/join
   // events; stage profiling events
   hipStream_t side_stream = nullptr;
+  bool concurrent = true;        // near field on the second stream
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool prof = false;
   double prof_ms[7] = {0, 0, 0, 0, 0, 0, 0};

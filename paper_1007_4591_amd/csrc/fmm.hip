@@ -11,6 +11,7 @@
 // reproducible run to run.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -31,7 +32,6 @@ struct PrecBufs {
   DBuf<char> E;                 // real [nleaf * 4 * ps]
   DBuf<double> dbg_near, dbg_far;  // sorted-order raw fields (debug)
   DBuf<double> near_out;           // near field per target (sorted order)
-  DBuf<char> sym_part;             // symmetric near-field partial sums (real)
   int last_tgt = 0;
   bool have = false;
 };
@@ -601,8 +601,6 @@ struct P2PArgs {
   double *y;
   double *dbg_near, *dbg_far;  // sorted order, may be NULL
   double *near_out;            // near field per target, sorted order ([n] or [4n])
-  const void *sym_part;        // symmetric partial sums (real) or NULL
-  const int32_t *sym_off, *sym_R;
 };
 
 // Near field (P2P).  One wave per chunk of up to 64 targets of one leaf.  A
@@ -735,117 +733,6 @@ __global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
   }
 }
 
-// Symmetric panel-panel near field (A: monopole sources, normal derivative
-// at the targets; A^T: dipole sources along the normals, potential).  The
-// radial factor 1/r^3 of a pair is shared by both directions, so each
-// unordered pair of near leaves (a, b) is evaluated once: the lanes hold up
-// to 64 targets of leaf a, the loop runs over the panels j of leaf b.
-//   forward (target i in a, source j in b): accumulated per lane;
-//   reverse (target j in b, source i in a): each lane's term goes to an LDS
-//     tile (64 sources x 64 lanes, padded stride 65), then lane jj adds row
-//     jj in lane order.
-// Results are per-entry partial sums (see sym_off) that the combination
-// kernel adds in entry order.  For the self pair (a, a) only the forward
-// direction is evaluated, with the i == j term removed by index.
-// Signs, with d = c_i - c_j and w = a x (monopole) or moment m = y n:
-//   A,  forward: -n_i . sum_j w_j d / r^3;   reverse: +sum_i w_i (n_j . d) / r^3
-//   A^T, forward: +sum_j (m_j . d) / r^3;    reverse: -sum_i (m_i . d) / r^3
-template <class R, int SRC>
-__global__ void __launch_bounds__(64) k_p2p_sym(const int4 *__restrict__ item1, const int4 *__restrict__ item2,
-                                                const int4 *__restrict__ leaf_range,
-                                                const int32_t *__restrict__ leaf_xyz,
-                                                const int32_t *__restrict__ sym_off,
-                                                const typename V4<R>::T *__restrict__ tpos,
-                                                const typename V4<R>::T *__restrict__ tnrm,
-                                                const typename V4<R>::T *__restrict__ spos,
-                                                const typename V4<R>::T *__restrict__ sdip, double sL_,
-                                                R *__restrict__ part) {
-  using R4 = typename V4<R>::T;
-  __shared__ R tile[64 * 65];
-  const int4 it = item1[blockIdx.x];
-  const int4 it2 = item2[blockIdx.x];
-  const int a = it.x, first = it.y, count = it.z, b = it.w;
-  const int e_ab = it2.x, e_ba = it2.y, chunk = it2.z;
-  const bool self = e_ba < 0;
-  const int lane = threadIdx.x;
-  const bool valid = lane < count;
-  const int i = first + (valid ? lane : 0);
-  const R4 tp = tpos[i];
-  const R4 me = spos[i];              // (rx, ry, rz, w_i)
-  R4 mi;                              // moment of panel i (A^T) or its normal (A)
-  if (SRC == SRC_PANEL_DIP) mi = sdip[i]; else mi = tnrm[i];
-  const int4 rb = leaf_range[b];
-  const int4 ra = leaf_range[a];
-  int axi, ayi, azi, bxi, byi, bzi;
-  xyz_of(leaf_xyz[a], axi, ayi, azi);
-  xyz_of(leaf_xyz[b], bxi, byi, bzi);
-  const R sL = (R)sL_;
-  const R ux = tp.x + R(axi - bxi) * sL, uy = tp.y + R(ayi - byi) * sL, uz = tp.z + R(azi - bzi) * sL;
-  const R wi = valid ? me.w : R(0);
-  R fx = R(0), fy = R(0), fz = R(0), fp = R(0);
-  const int nb = rb.y - rb.x;
-  const int rev_base = self ? 0 : sym_off[e_ba] + chunk * nb;
-  for (int j0 = rb.x; j0 < rb.y; j0 += 64) {
-    const int nblk = min(64, rb.y - j0);
-    if (self) {
-      for (int jj = 0; jj < nblk; ++jj) {
-        const int j = j0 + jj;
-        const R4 s4 = spos[j];
-        const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
-        const R r2 = dx * dx + dy * dy + dz * dz;
-        const R ri = (j == i) ? R(0) : rsq(r2);
-        const R ri3 = ri * ri * ri;
-        if (SRC == SRC_PANEL_MONO) {
-          const R t = s4.w * ri3;
-          fx += t * dx;
-          fy += t * dy;
-          fz += t * dz;
-        } else {
-          const R4 mj = sdip[j];
-          fp += (mj.x * dx + mj.y * dy + mj.z * dz) * ri3;
-        }
-      }
-    } else {
-#pragma unroll 2
-      for (int jj = 0; jj < nblk; ++jj) {
-        const int j = j0 + jj;
-        const R4 s4 = spos[j];
-        const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
-        const R r2 = dx * dx + dy * dy + dz * dz;
-        const R ri = rsq(r2);
-        const R ri3 = ri * ri * ri;
-        R c;
-        if (SRC == SRC_PANEL_MONO) {
-          const R t = s4.w * ri3;
-          fx += t * dx;
-          fy += t * dy;
-          fz += t * dz;
-          const R4 nj = tnrm[j];
-          c = wi * ri3 * (nj.x * dx + nj.y * dy + nj.z * dz);
-        } else {
-          const R4 mj = sdip[j];
-          fp += (mj.x * dx + mj.y * dy + mj.z * dz) * ri3;
-          c = valid ? -(mi.x * dx + mi.y * dy + mi.z * dz) * ri3 : R(0);
-        }
-        tile[jj * 65 + lane] = c;
-      }
-      __syncthreads();
-      if (lane < nblk) {
-        R acc = R(0);
-        for (int l = 0; l < count; ++l) acc += tile[lane * 65 + l];
-        part[rev_base + (j0 + lane - rb.x)] = acc;
-      }
-      __syncthreads();
-    }
-  }
-  if (valid) {
-    R v;
-    if (SRC == SRC_PANEL_MONO) v = -(mi.x * fx + mi.y * fy + mi.z * fz);
-    else v = fp;
-    part[sym_off[e_ab] + (i - ra.x)] = v;
-  }
-}
-
 // Far field (L2P from the leaf's evaluation coefficients, read through the
 // scalar cache) plus the near field, combined into the operator's output in
 // the caller's order: y = alpha x + beta (area) field.
@@ -886,31 +773,13 @@ __global__ void __launch_bounds__(64) k_l2p_combine(P2PArgs a) {
   const int64_t u = a.tperm[ti];
   double res[4], near_v, far_v;
   int nres = 1;
-  double nsym = 0.0;
-  if (a.sym_part) {
-    // the target's partial sums, entry by entry (compensated)
-    const R *part = reinterpret_cast<const R *>(a.sym_part);
-    const int4 lr = a.leaf_range[leaf];
-    const int nt = lr.y - lr.x, il = ti - lr.x;
-    R s_ = R(0), c_ = R(0);
-    for (int e = a.near_ptr[leaf]; e < a.near_ptr[leaf + 1]; ++e) {
-      const int base = a.sym_off[e] + il;
-      for (int r = 0; r < a.sym_R[e]; ++r) {
-        const R y_ = part[base + r * nt] - c_;
-        const R t_ = s_ + y_;
-        c_ = (t_ - s_) - y_;
-        s_ = t_;
-      }
-    }
-    nsym = (double)s_;
-  }
   if (OUT == OUT_POT) {
-    near_v = a.sym_part ? nsym : a.near_out[ti];
+    near_v = a.near_out[ti];
     far_v = (double)fp;
     res[0] = near_v + far_v;
   } else if (OUT == OUT_NGRAD) {
     const R4 nn = reinterpret_cast<const R4 *>(a.tgt_nrm)[ti];
-    near_v = a.sym_part ? nsym : a.near_out[ti];
+    near_v = a.near_out[ti];
     far_v = (double)nn.x * fgx + (double)nn.y * fgy + (double)nn.z * fgz;
     res[0] = near_v + far_v;
   } else {
@@ -1016,7 +885,6 @@ static PrecBufs &bufs(Tree &T, int prec, hipStream_t s) {
     pb->dbg_near.alloc(npts);
     pb->dbg_far.alloc(npts);
     pb->near_out.alloc(4 * npts);
-    pb->sym_part.alloc((size_t)std::max<int64_t>(T.n_sym_slots, 1) * rs);
     pb->M.zero(s);
     pb->L.zero(s);
     pb->E.zero(s);
@@ -1117,34 +985,11 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   a.dbg_far = B.dbg_far.p;
   a.near_out = B.near_out.p;
   B.last_tgt = rq.tgt;
-  const bool sym = !tgt_ch && (rq.src == SRC_PANEL_MONO || rq.src == SRC_PANEL_DIP) && T.n_sym_items > 0 &&
-                   T.use_sym;
-  a.sym_part = nullptr;
-  if (sym) {
-    a.sym_part = B.sym_part.p;
-    a.sym_off = T.sym_off.p;
-    a.sym_R = T.sym_R.p;
-  }
-  if (sym) {
-    HIP_OK(hipStreamWaitEvent(T.side_stream, T.ev_fork, 0));
-    const hipStream_t ss = T.side_stream;
-    prof_begin(T, ST_P2P, ss);
-    R *part = reinterpret_cast<R *>(B.sym_part.p);
-    const R4 *tp = reinterpret_cast<const R4 *>(a.tgt_pos), *tn = reinterpret_cast<const R4 *>(a.tgt_nrm);
-    if (rq.src == SRC_PANEL_MONO)
-      k_p2p_sym<R, SRC_PANEL_MONO><<<T.n_sym_items, 64, 0, ss>>>(T.sym_item.p, T.sym_item2.p, a.leaf_range,
-                                                                  a.leaf_xyz, T.sym_off.p, tp, tn, spos, sdip, sL,
-                                                                  part);
-    else
-      k_p2p_sym<R, SRC_PANEL_DIP><<<T.n_sym_items, 64, 0, ss>>>(T.sym_item.p, T.sym_item2.p, a.leaf_range,
-                                                                 a.leaf_xyz, T.sym_off.p, tp, tn, spos, sdip, sL,
-                                                                 part);
-    LAUNCH_OK();
-    prof_end(T, ST_P2P, ss);
-    HIP_OK(hipEventRecord(T.ev_join, ss));
-  } else if (nchunks > 0) {
-    HIP_OK(hipStreamWaitEvent(T.side_stream, T.ev_fork, 0));
-    const hipStream_t ss = T.side_stream;
+  if (nchunks > 0) {
+    // The near field runs on the second stream beside P2P-M2M: those passes
+    // leave most of the chip idle (few cells per level, LDS-bound P2M).
+    const hipStream_t ss = T.concurrent ? T.side_stream : s;
+    HIP_OK(hipStreamWaitEvent(ss, T.ev_fork, 0));
     prof_begin(T, ST_P2P, ss);
 #define P2P_CALL(S, Tg, O) k_p2p_near<R, S, Tg, O><<<nchunks, 64, 0, ss>>>(a)
     if (!tgt_ch) {
@@ -1258,6 +1103,7 @@ void fmm_apply(Tree &T, int precision, const FmmRequest &rq, hipStream_t s) {
     HIP_OK(hipEventCreateWithFlags(&T.ev_join, hipEventDisableTiming));
     HIP_OK(hipStreamCreateWithFlags(&T.side_stream, hipStreamNonBlocking));  // default priority
     T.ev_init = true;
+    if (const char *e = getenv("BEMFMM_CONCURRENT_P2P")) T.concurrent = atoi(e) != 0;
   }
   if (prec == BEMFMM_FP64)
     run_fmm<double>(T, B, rq, s);

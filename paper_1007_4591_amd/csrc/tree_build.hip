@@ -552,75 +552,6 @@ __global__ void k_combo_compact(const int32_t *__restrict__ order, const uint32_
   }
 }
 
-// ---- symmetric near-field bookkeeping (leaf level)
-
-__global__ void k_entry_target(const int32_t *__restrict__ near_ptr, int64_t C, int32_t *__restrict__ ent_t) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= C) return;
-  for (int e = near_ptr[t]; e < near_ptr[t + 1]; ++e) ent_t[e] = (int32_t)t;
-}
-
-__device__ inline int nchunks64(int n) { return (n + 63) / 64; }
-
-// lane-leaf choice for an unordered pair: the better lane utilisation
-// (count / 64 per chunk), ties to the larger count, then the smaller index.
-// Symmetric in (t, s), so both entries of a pair agree.
-__device__ inline bool lanes_are_t(int t, int nt, int s, int ns) {
-  const long long ut = (long long)nt * (64LL * nchunks64(ns));
-  const long long us = (long long)ns * (64LL * nchunks64(nt));
-  if (ut != us) return ut > us;
-  if (nt != ns) return nt > ns;
-  return t < s;
-}
-
-__global__ void k_sym_entries(const int32_t *__restrict__ ent_t, const int32_t *__restrict__ near_ptr,
-                              const int32_t *__restrict__ near_idx, const int4 *__restrict__ range, int64_t nE,
-                              int32_t *__restrict__ rev, int32_t *__restrict__ R, int32_t *__restrict__ slots,
-                              int32_t *__restrict__ nitems) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nE) return;
-  const int t = ent_t[e], s = near_idx[e];
-  // reverse entry: position of t in s's sorted list
-  int lo = near_ptr[s], hi = near_ptr[s + 1];
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (near_idx[mid] < t) lo = mid + 1; else hi = mid;
-  }
-  rev[e] = lo;
-  const int nt = range[t].y - range[t].x, ns = range[s].y - range[s].x;
-  int r = 1, items = 0;
-  if (t == s) {
-    items = nchunks64(nt);
-  } else if (lanes_are_t(t, nt, s, ns)) {
-    items = nchunks64(nt);
-  } else {
-    r = nchunks64(ns);
-  }
-  if (nt == 0 || ns == 0) {  // nothing to exchange with a leaf without panels
-    items = 0;
-    r = 0;
-  }
-  R[e] = r;
-  slots[e] = nt * r;
-  nitems[e] = items;
-}
-
-__global__ void k_sym_items(const int32_t *__restrict__ ent_t, const int32_t *__restrict__ near_idx,
-                            const int32_t *__restrict__ rev, const int4 *__restrict__ range, int64_t nE,
-                            const int32_t *__restrict__ ipos, int4 *__restrict__ it1, int4 *__restrict__ it2) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nE) return;
-  const int t = ent_t[e], s = near_idx[e];
-  const int nt = range[t].y - range[t].x, ns = range[s].y - range[s].x;
-  if (nt == 0 || ns == 0) return;
-  if (t != s && !lanes_are_t(t, nt, s, ns)) return;
-  int k = ipos[e];
-  for (int c = 0; c * 64 < nt; ++c, ++k) {
-    it1[k] = make_int4(t, range[t].x + 64 * c, min(64, nt - 64 * c), s);
-    it2[k] = make_int4((int)e, t == s ? -1 : rev[e], c, 0);
-  }
-}
-
 __global__ void k_far_ptr(const int32_t *__restrict__ cnt_scan, int32_t C, int64_t cl, int64_t foff,
                           int32_t *__restrict__ far_ptr) {
   int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1199,37 +1130,6 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     HIP_OK(hipMemcpyAsync(&h, acc.p, 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     T.p2p_pairs_pp = (int64_t)h;
-  }
-  // symmetric panel-panel near field: slots and work items
-  {
-    const int64_t nE = T.n_near_leaf;
-    const int32_t *nptr = T.near_ptr.p + T.near_ptr_off[L];
-    const int32_t *nidx = T.near_idx.p + T.near_off[L];
-    const int4 *rg = T.crange.p + T.coff[L];
-    DBuf<int32_t> ent, rev, slots, nitems, ipos;
-    ent.alloc(std::max<int64_t>(nE, 1));
-    rev.alloc(std::max<int64_t>(nE, 1));
-    slots.alloc(nE + 1);
-    nitems.alloc(nE + 1);
-    ipos.alloc(nE + 1);
-    T.sym_R.alloc(std::max<int64_t>(nE, 1));
-    T.sym_off.alloc(nE + 1);
-    k_entry_target<<<cdiv(CL, TB), TB, 0, s>>>(nptr, CL, ent.p);
-    LAUNCH_OK();
-    k_sym_entries<<<cdiv(nE, TB), TB, 0, s>>>(ent.p, nptr, nidx, rg, nE, rev.p, T.sym_R.p, slots.p, nitems.p);
-    LAUNCH_OK();
-    HIP_OK(hipMemsetAsync(slots.p + nE, 0, 4, s));
-    HIP_OK(hipMemsetAsync(nitems.p + nE, 0, 4, s));
-    int32_t nslots = 0, nit = 0;
-    exclusive_scan_i32(slots.p, T.sym_off.p, nE + 1, s, &nslots);
-    exclusive_scan_i32(nitems.p, ipos.p, nE + 1, s, &nit);
-    T.n_sym_slots = nslots;
-    T.n_sym_items = nit;
-    T.sym_item.alloc(std::max<int32_t>(nit, 1));
-    T.sym_item2.alloc(std::max<int32_t>(nit, 1));
-    k_sym_items<<<cdiv(nE, TB), TB, 0, s>>>(ent.p, nidx, rev.p, rg, nE, ipos.p, T.sym_item.p, T.sym_item2.p);
-    LAUNCH_OK();
-    HIP_OK(hipStreamSynchronize(s));
   }
   // P2P chunks: at most 64 targets of one leaf per wave; a chunk of n < 64
   // targets splits the sources over 64 / n lane groups
