@@ -177,6 +177,14 @@ int bemfmm_adjoint_grad(bemfmm_tree *tree, const double *q, const double *x, dou
 /* Thread-local message for the last failure on this thread ("" if none). */
 const char *bemfmm_last_error(void);
 
+/* Device memory of destroyed trees and of grown workspaces is kept by the
+ * library, per device, and reused by later builds of a similar size (up to
+ * BEMFMM_CACHE_LIMIT_MB per device, default 32768; a failed allocation
+ * empties the cache and retries).  This call returns every cached block of
+ * every device to the driver after synchronising each device; memory of
+ * live trees is untouched. */
+int bemfmm_release_cache(void);
+
 /* ----------------------------------------------------------------------
  * Inspection (used by parity tests; not needed to solve).
  * ---------------------------------------------------------------------- */

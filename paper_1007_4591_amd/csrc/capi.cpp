@@ -179,6 +179,10 @@ int bemfmm_adjoint_grad(bemfmm_tree *tree, const double *q, const double *x, dou
 
 const char *bemfmm_last_error(void) { return g_err.c_str(); }
 
+int bemfmm_release_cache(void) {
+  return guard([&] { dev_cache_release(); });
+}
+
 int bemfmm_tree_export(const bemfmm_tree *tree, int32_t *panel_perm, int32_t *charge_perm, uint32_t *panel_key,
                        uint32_t *charge_key, uint32_t *cell_key, int32_t *cell_level, int32_t *cell_range,
                        int32_t *cell_parent, int32_t *near_ptr, int32_t *near_idx, int32_t *far_pairs) {

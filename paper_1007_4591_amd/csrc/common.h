@@ -56,6 +56,12 @@ void set_error(const std::string &msg);
 
 #define LAUNCH_OK() HIP_OK(hipGetLastError())
 
+// Caching device allocator (alloc.cpp): blocks freed by one tree are reused
+// by the next build of a similar size instead of going back to the driver.
+void *dev_alloc(size_t bytes);
+void dev_free(void *p) noexcept;
+void dev_cache_release();
+
 // Owning device buffer.
 template <class T>
 struct DBuf {
@@ -66,7 +72,7 @@ struct DBuf {
   DBuf &operator=(const DBuf &) = delete;
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
     p = nullptr;
     n = 0;
   }
@@ -74,7 +80,7 @@ struct DBuf {
     if (count == n && p) return;
     release();
     if (count == 0) return;
-    HIP_OK(hipMalloc((void **)&p, count * sizeof(T)));
+    p = static_cast<T *>(dev_alloc(count * sizeof(T)));
     n = count;
   }
   // grow only

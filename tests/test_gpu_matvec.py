@@ -167,3 +167,29 @@ def test_near_and_far_fields(prec):
         tol_n = 1e-12 if prec == 0 else 2e-6
         assert abs(near[i] - want_near) <= tol_n * np.abs(Kall).max(), i
         assert abs(far[i] - want_far) <= 1e-6 * np.abs(Kall).max(), i
+
+
+def test_rebuild_after_destroy_reuses_memory_bitwise():
+    """Device blocks of a destroyed tree are reused by the next builds (a
+    smaller tree in between, then the same one); results must be bitwise
+    those of the first build, also after the cache has been emptied."""
+    B = lib()
+    big, small = synth.blobby(5), synth.kirkwood(3, n_charges=30)
+    x = _inputs(big)[0]
+    xs = _inputs(small)[0]
+    gs = oracle.geometry(small.verts, small.tris)
+    outs = []
+    for stage in ("first", "after-small", "after-release"):
+        t = B.build_tree(big.verts, big.tris, big.charge_pos, B.Params())
+        outs.append([host(B.fmm_matvec(t, 0, prec, dev(x))) for prec in (0, 1)])
+        B.tree_destroy(t)
+        ts = B.build_tree(small.verts, small.tris, small.charge_pos, B.Params(ncrit=16))
+        e = rel_l2(host(B.fmm_matvec(ts, 0, 0, dev(xs))), oracle.apply_A(gs, F, xs))
+        print(f"[rebuild] {stage} small-tree err={e:.3e}", flush=True)
+        assert e <= 1e-5
+        B.tree_destroy(ts)
+        if stage == "after-small":
+            B.release_cache()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
