@@ -176,8 +176,11 @@ struct Tree {
   // holds sources and whose target cell holds targets of that kind are kept;
   // they are sorted by translation offset (all levels together).
   struct M2LList {
-    DBuf<int32_t> order;             // kept pair indices, offset-sorted (= M2L output row order)
-    DBuf<int32_t> pos;               // pair index -> output row, or -1 if not kept
+    DBuf<int32_t> src;               // source cell (global index) of each kept pair, offset-sorted
+                                     // (= M2L output row order)
+    DBuf<int32_t> dest;              // output row of each kept pair: rows are in pair order
+                                     // (level, target, source), so a cell's rows are contiguous
+    DBuf<int32_t> kptr;              // [cells + 1] first output row of each cell
     DBuf<int32_t> group_off;         // per offset group: compact offset id
     DBuf<int32_t> group_end;         // per group: end row
     DBuf<int32_t> tile_group, tile_row;      // FP32 tiles of M2L_ROWS32 rows
@@ -191,8 +194,21 @@ struct Tree {
   const Tables *tab = nullptr;
   const float *t_m2l32 = nullptr;   // [noff][PS/4 kk][PS/16 ct][64 lanes], MFMA B-operand order
   const double *t_m2l64 = nullptr;  // same layout
-  const float *t_m2m32 = nullptr, *t_l2l32 = nullptr;   // [8][ps in][ps out] (transposed)
-  const double *t_m2m64 = nullptr, *t_l2l64 = nullptr;
+  const float *t_m2m32 = nullptr;   // [8][ps in][ps out] (transposed)
+  const double *t_m2m64 = nullptr;
+  const float *t_l2l32 = nullptr;   // [8 octants][PS/4 kk][PS/16 ct][64 lanes], MFMA B-operand order
+  const double *t_l2l64 = nullptr;
+
+  // L2L as batched MFMA products, per level l >= 3: rows are the level's
+  // cells grouped by octant (the operator depends on the octant only);
+  // src = parent cell (global index), dest = cell index within the level.
+  // Tiles of level l are [t0[l], t1[l]) (FP32) and [t0_64[l], t1_64[l]).
+  struct L2LList {
+    DBuf<int32_t> src, dest, group_off, group_end;
+    DBuf<int32_t> tile_group, tile_row, tile_group64, tile_row64;
+    std::vector<int64_t> t0, t1, t0_64, t1_64;
+    int64_t max_cells = 0;
+  } l2lw;
 
   // P2P work decomposition: (leaf, first sorted index, count, lane groups)
   // per chunk of at most 64 targets of one leaf

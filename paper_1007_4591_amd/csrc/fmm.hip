@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 
 #include "common.h"
 
@@ -29,6 +30,7 @@ struct PrecBufs {
   DBuf<char> src_pos, src_dip;  // real4 [max(N, Q)]
   DBuf<char> M, L;              // real [ncell_tot * ps]
   DBuf<char> m2l_out;           // real [nfar * ps]
+  DBuf<char> l2l_out;           // real [cells of the largest level * ps]
   DBuf<char> E;                 // real [nleaf * 4 * ps]
   DBuf<double> dbg_near, dbg_far;  // sorted-order raw fields (debug)
   DBuf<double> near_out;           // near field per target (sorted order)
@@ -250,130 +252,115 @@ __global__ void __launch_bounds__(64) k_m2m(int np2, int ps, int64_t c0, int64_t
 // levels together: the scaled operator depends on the offset only).  Each
 // wave computes, for RT row tiles of 16 pairs,
 //   D[16 x 16*NT] += A[16 x 4] * B[4 x 16*NT]   for every k-step,
-// A = gathered source expansions, B = T_o^T read once per k-step and reused
-// by the RT row tiles.  The K dimension is permuted so that each lane reads
-// a contiguous quarter of its source row: at k-step kk, lane group
-// g = lane/16 supplies input g*KK + kk (the B table is stored in that order).
-// Results are written in the sorted (offset-group) order, so each wave
-// stores RT*16 contiguous rows; the downward pass gathers them per target in
-// a fixed order.  Output layouts (checked on the device): FP32 16x16x4 puts
+// A = gathered source expansions (held in registers for the whole tile),
+// B = T_o^T read once per k-step and reused by the RT row tiles.  The K
+// dimension is permuted so that each lane reads a contiguous quarter of its
+// source row: at k-step kk, lane group g = lane/16 supplies input g*KK + kk
+// (the B table is stored in that order).  Rows past the end of the group
+// repeat its last row (MFMA rows are independent; they are not stored).
+// Registers are budgeted for two waves per SIMD so that one wave's gather
+// overlaps the other's MFMA work.  With BLDS the four waves of a tile share
+// the operator through LDS instead of each reading it from L2.
+// Each result row goes to its place in pair order (level, target, source),
+// so that the downward pass reads a cell's rows as one contiguous run.  Output layouts (checked on the device): FP32 16x16x4 puts
 // D[4*(lane/16) + q][lane%16] in register q; FP64 16x16x4 puts
 // D[lane/16 + 4*q][lane%16] in register q.
-template <int NT, int RT>
-__global__ void __launch_bounds__(256) k_m2l_f32(const int32_t *__restrict__ tile_group,
-                                                 const int32_t *__restrict__ tile_row,
-                                                 const int32_t *__restrict__ group_off,
-                                                 const int32_t *__restrict__ group_end,
-                                                 const int32_t *__restrict__ order, const int2 *__restrict__ ts,
-                                                 const float *__restrict__ Tsw, const float *__restrict__ M,
-                                                 float *__restrict__ out) {
+template <class R, int NT, int RT, bool BLDS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_m2l(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ tile_row,
+      const int32_t *__restrict__ group_off, const int32_t *__restrict__ group_end, const int32_t *__restrict__ src,
+      const int32_t *__restrict__ dest, const R *__restrict__ Tsw, const R *__restrict__ M, R *__restrict__ out) {
+  constexpr bool F64 = sizeof(R) == 8;
+  constexpr int W = 16 / sizeof(R);
   constexpr int PS = NT * 16;
   constexpr int KK = PS / 4;
+  constexpr int TB = KK * NT * 64;  // reals of one offset's operator
+  using V16 = typename std::conditional<F64, double2, float4>::type;
+  using Acc = typename std::conditional<F64, f64x4, f32x4>::type;
+  __shared__ V16 Bs[BLDS ? TB / W : 1];
+  __shared__ int Ds[BLDS ? 4 * 16 * RT : 1];
   const int tile = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = tile_group[tile];
   const int end = group_end[g];
   const int row0 = tile_row[tile] + wave * (16 * RT);
-  if (row0 >= end) return;
+  const bool active = row0 < end;
+  if (!BLDS && !active) return;
   const int off = group_off[g];
   const int i = lane & 15, kq = lane >> 4;
-  // A operands: this lane's quarter of the source row of each row tile
-  float a[RT][KK];
+  int sr[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) sr[rt] = src[min(row0 + rt * 16 + i, end - 1)];
+  // output rows of the rows this lane stores (-1 past the end); with BLDS
+  // they are staged in LDS with the operator
+  int dr[RT][4];
+  if constexpr (!BLDS) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rr = row0 + rt * 16 + (F64 ? kq + 4 * q : 4 * kq + q);
+        dr[rt][q] = rr < end ? dest[rr] : -1;
+      }
+  }
+  R a[RT][KK];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
-    const int r = row0 + rt * 16 + i;
-    if (r < end) {
-      const int src = ts[order[r]].y;
-      const float4 *Ms = reinterpret_cast<const float4 *>(M + (size_t)src * PS + kq * KK);
+    const V16 *Ms = reinterpret_cast<const V16 *>(M + (size_t)sr[rt] * PS + kq * KK);
 #pragma unroll
-      for (int v = 0; v < KK / 4; ++v) {
-        const float4 t = Ms[v];
+    for (int v = 0; v < KK / W; ++v) {
+      const V16 t = Ms[v];
+      if constexpr (F64) {
+        a[rt][2 * v] = t.x;
+        a[rt][2 * v + 1] = t.y;
+      } else {
         a[rt][4 * v] = t.x;
         a[rt][4 * v + 1] = t.y;
         a[rt][4 * v + 2] = t.z;
         a[rt][4 * v + 3] = t.w;
       }
-    } else {
-#pragma unroll
-      for (int v = 0; v < KK; ++v) a[rt][v] = 0.f;
     }
   }
-  f32x4 acc[RT][NT];
+  const R *B;
+  if constexpr (BLDS) {
+    const V16 *Bg = reinterpret_cast<const V16 *>(Tsw + (size_t)off * TB);
+    for (int v = threadIdx.x; v < TB / W; v += 256) Bs[v] = Bg[v];
+    for (int v = threadIdx.x; v < 4 * 16 * RT; v += 256) {
+      const int rr = tile_row[tile] + v;
+      Ds[v] = rr < end ? dest[rr] : -1;
+    }
+    __syncthreads();
+    if (!active) return;
+    B = reinterpret_cast<const R *>(Bs) + lane;
+  } else {
+    B = Tsw + (size_t)off * TB + lane;
+  }
+  Acc acc[RT][NT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const float *B = Tsw + (size_t)off * KK * NT * 64 + lane;
+    for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = Acc{0, 0, 0, 0};
 #pragma unroll
   for (int kk = 0; kk < KK; ++kk) {
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) {
-      const float b = B[(kk * NT + ct) * 64];
+      const R b = B[(kk * NT + ct) * 64];
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][kk], b, acc[rt][ct], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int rr = row0 + rt * 16 + 4 * kq + q;
-      if (rr < end) {
-        float *o = out + (size_t)rr * PS + i;
-#pragma unroll
-        for (int ct = 0; ct < NT; ++ct) o[ct * 16] = acc[rt][ct][q];
+      for (int rt = 0; rt < RT; ++rt) {
+        if constexpr (F64)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt][kk], b, acc[rt][ct], 0, 0, 0);
+        else
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][kk], b, acc[rt][ct], 0, 0, 0);
       }
     }
-}
-
-template <int NT, int RT>
-__global__ void __launch_bounds__(256) k_m2l_f64(const int32_t *__restrict__ tile_group,
-                                                 const int32_t *__restrict__ tile_row,
-                                                 const int32_t *__restrict__ group_off,
-                                                 const int32_t *__restrict__ group_end,
-                                                 const int32_t *__restrict__ order, const int2 *__restrict__ ts,
-                                                 const double *__restrict__ Tsw, const double *__restrict__ M,
-                                                 double *__restrict__ out) {
-  constexpr int PS = NT * 16;
-  constexpr int KK = PS / 4;
-  const int tile = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = tile_group[tile];
-  const int end = group_end[g];
-  const int row0 = tile_row[tile] + wave * (16 * RT);
-  if (row0 >= end) return;
-  const int off = group_off[g];
-  const int i = lane & 15, kq = lane >> 4;
-  const double *Ms[RT];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    const int r = row0 + rt * 16 + i;
-    Ms[rt] = (r < end) ? M + (size_t)ts[order[r]].y * PS + kq * KK : nullptr;
-  }
-  f64x4 acc[RT][NT];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const double *B = Tsw + (size_t)off * KK * NT * 64 + lane;
-  for (int kk = 0; kk < KK; ++kk) {
-    double av[RT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) av[rt] = Ms[rt] ? Ms[rt][kk] : 0.0;
-#pragma unroll
-    for (int ct = 0; ct < NT; ++ct) {
-      const double b = B[(kk * NT + ct) * 64];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rt], b, acc[rt][ct], 0, 0, 0);
-    }
   }
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int rr = row0 + rt * 16 + kq + 4 * q;
-      if (rr < end) {
-        double *o = out + (size_t)rr * PS + i;
+      const int d = BLDS ? Ds[wave * 16 * RT + rt * 16 + (F64 ? kq + 4 * q : 4 * kq + q)] : dr[rt][q];
+      if (d >= 0) {
+        R *o = out + (size_t)d * PS + i;
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) o[ct * 16] = acc[rt][ct][q];
       }
@@ -387,20 +374,21 @@ template <> struct VecT<float> { using T = float4; static constexpr int W = 4; }
 template <> struct VecT<double> { using T = double2; static constexpr int W = 2; };
 
 // One wave per cell of level l: L = L2L(parent) + sum of the cell's M2L
-// results.  The results of the cell's pairs are gathered (rows of ps reals,
-// located through far_pos) with vector loads: a row takes ps/W lanes, so
-// several pairs are read per step by lane groups; every lane keeps a
-// compensated sum and the groups are added in group order.  At the leaf
-// level the kernel also writes the evaluation coefficients E[leaf][4][ps]
-// of the potential and of its gradient (see L2P).
+// results.  The cell's result rows are one contiguous run (kptr), read with
+// vector loads: a row takes ps/W lanes, so several rows are read per step
+// by lane groups, U rows in flight per group; every lane keeps a compensated
+// sum, and the groups are added in group order; the L2L term (a batched
+// MFMA product per level, l2l[cell of the level][ps]) is added last.  At the
+// leaf level the kernel also writes the evaluation coefficients
+// E[leaf][4][ps] of the potential and of its gradient (see L2P).
 template <class R>
 __global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int64_t C, int with_parent,
-                                                 const int32_t *__restrict__ parent, const uint32_t *__restrict__ ckey,
-                                                 const R *__restrict__ St, const int32_t *__restrict__ far_ptr,
-                                                 const int32_t *__restrict__ far_pos, const R *__restrict__ m2l,
-                                                 R *__restrict__ Lx, int leaf, R inv_s, R *__restrict__ E) {
+                                                 const R *__restrict__ l2l, const int32_t *__restrict__ kptr,
+                                                 const R *__restrict__ m2l, R *__restrict__ Lx, int leaf, R inv_s,
+                                                 R *__restrict__ E) {
   using VT = typename VecT<R>::T;
   constexpr int W = VecT<R>::W;
+  constexpr int U = 8;
   extern __shared__ char smem_raw[];
   R *Ls = reinterpret_cast<R *>(smem_raw);     // [ps]
   R *part = Ls + ps;                          // [64 * W] group partials
@@ -415,21 +403,16 @@ __global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int6
   R s[W], comp[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) s[w] = comp[w] = R(0);
-  const int b = far_ptr[c], e = far_ptr[c + 1];
+  const int b = kptr[c], e = kptr[c + 1];
   if (act) {
-    // four rows in flight per lane group, added in order
+    const VT *rows = reinterpret_cast<const VT *>(m2l) + k4;
     int q = b + grp;
-    for (; q + 3 * groups < e; q += 4 * groups) {
-      int rows[4];
-      VT v[4];
+    for (; q + (U - 1) * groups < e; q += U * groups) {
+      VT v[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) rows[u] = far_pos[q + u * groups];
+      for (int u = 0; u < U; ++u) v[u] = rows[(size_t)(q + u * groups) * lpr];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (rows[u] >= 0) v[u] = reinterpret_cast<const VT *>(m2l + (size_t)rows[u] * ps)[k4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (rows[u] < 0) continue;  // pair not in this product's list
+      for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int w = 0; w < W; ++w) {
           const R y = reinterpret_cast<const R *>(&v[u])[w] - comp[w];
@@ -437,12 +420,9 @@ __global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int6
           comp[w] = (t - s[w]) - y;
           s[w] = t;
         }
-      }
     }
     for (; q < e; q += groups) {
-      const int row = far_pos[q];
-      if (row < 0) continue;
-      const VT v = reinterpret_cast<const VT *>(m2l + (size_t)row * ps)[k4];
+      const VT v = rows[(size_t)q * lpr];
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         const R y = reinterpret_cast<const R *>(&v)[w] - comp[w];
@@ -469,24 +449,8 @@ __global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int6
   }
   __syncthreads();
   if (with_parent) {
-    const int pc = parent[c];
-    const int oct = ckey[c] & 7;
-    const R *S = St + (size_t)oct * ps * ps;
-    const R *Lp = Lx + (size_t)pc * ps;
-    R a[3] = {R(0), R(0), R(0)};
-    for (int j = 0; j < np2; ++j) {
-      const R lj = Lp[j];
-#pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        const int k = lane + 64 * t;
-        if (k < ps) a[t] += S[(size_t)j * ps + k] * lj;
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const int k = lane + 64 * t;
-      if (k < ps) Ls[k] += a[t];
-    }
+    const R *Lc = l2l + (size_t)blockIdx.x * ps;
+    for (int k = lane; k < ps; k += 64) Ls[k] += Lc[k];
   }
   __syncthreads();
   R *out = Lx + (size_t)c * ps;
@@ -881,6 +845,7 @@ static PrecBufs &bufs(Tree &T, int prec, hipStream_t s) {
     pb->M.alloc((size_t)T.ncell_tot * T.ps * rs);
     pb->L.alloc((size_t)T.ncell_tot * T.ps * rs);
     pb->m2l_out.alloc((size_t)std::max<int64_t>(T.nfar, 1) * T.ps * rs);
+    pb->l2l_out.alloc((size_t)std::max<int64_t>(T.l2lw.max_cells, 1) * T.ps * rs);
     pb->E.alloc((size_t)T.ncell[T.L] * 4 * T.ps * rs);
     pb->dbg_near.alloc(npts);
     pb->dbg_far.alloc(npts);
@@ -1035,12 +1000,12 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
 #define M2L_CASE(nt)                                                                                           \
   case nt:                                                                                                     \
     if (f64)                                                                                                   \
-      k_m2l_f64<nt, M2L_RT64><<<dim3((unsigned)ML.ntiles64), 256, 0, s>>>(                                     \
-          ML.tile_group64.p, ML.tile_row64.p, ML.group_off.p, ML.group_end.p, ML.order.p, T.far_ts.p,          \
-          T.t_m2l64, reinterpret_cast<const double *>(M), reinterpret_cast<double *>(m2l));                    \
+      k_m2l<double, nt, M2L_RT64, false><<<dim3((unsigned)ML.ntiles64), 256, 0, s>>>(                         \
+          ML.tile_group64.p, ML.tile_row64.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p, T.t_m2l64,             \
+          reinterpret_cast<const double *>(M), reinterpret_cast<double *>(m2l));                               \
     else                                                                                                       \
-      k_m2l_f32<nt, M2L_RT32><<<dim3((unsigned)ML.ntiles), 256, 0, s>>>(                                       \
-          ML.tile_group.p, ML.tile_row.p, ML.group_off.p, ML.group_end.p, ML.order.p, T.far_ts.p, T.t_m2l32,  \
+      k_m2l<float, nt, M2L_RT32, true><<<dim3((unsigned)ML.ntiles), 256, 0, s>>>(                              \
+          ML.tile_group.p, ML.tile_row.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p, T.t_m2l32,                 \
           reinterpret_cast<const float *>(M), reinterpret_cast<float *>(m2l));                                 \
     break;
       switch (NT) {
@@ -1061,13 +1026,44 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     prof_end(T, ST_M2L, s);
     // downward pass, levels 2 .. L
     prof_begin(T, ST_L2L, s);
-    const R *Sl = f64 ? reinterpret_cast<const R *>(T.t_l2l64) : reinterpret_cast<const R *>(T.t_l2l32);
+    const Tree::L2LList &LW = T.l2lw;
+    R *l2l = reinterpret_cast<R *>(B.l2l_out.p);
     for (int l = 2; l <= L; ++l) {
       const bool leaf = (l == L);
+      if (l > 2) {
+        // L2L of every cell of level l from its parent's final expansion
+        const int64_t t0 = f64 ? LW.t0_64[l] : LW.t0[l], t1 = f64 ? LW.t1_64[l] : LW.t1[l];
+        if (t1 > t0) {
+#define L2L_CASE(nt)                                                                                           \
+  case nt:                                                                                                     \
+    if (f64)                                                                                                   \
+      k_m2l<double, nt, M2L_RT64, false><<<dim3((unsigned)(t1 - t0)), 256, 0, s>>>(                           \
+          LW.tile_group64.p + t0, LW.tile_row64.p + t0, LW.group_off.p, LW.group_end.p, LW.src.p, LW.dest.p,   \
+          T.t_l2l64, reinterpret_cast<const double *>(Lx), reinterpret_cast<double *>(l2l));                   \
+    else                                                                                                       \
+      k_m2l<float, nt, M2L_RT32, true><<<dim3((unsigned)(t1 - t0)), 256, 0, s>>>(                              \
+          LW.tile_group.p + t0, LW.tile_row.p + t0, LW.group_off.p, LW.group_end.p, LW.src.p, LW.dest.p,       \
+          T.t_l2l32, reinterpret_cast<const float *>(Lx), reinterpret_cast<float *>(l2l));                     \
+    break;
+          switch (NT) {
+            L2L_CASE(1)
+            L2L_CASE(2)
+            L2L_CASE(3)
+            L2L_CASE(4)
+            L2L_CASE(5)
+            L2L_CASE(6)
+            L2L_CASE(7)
+            L2L_CASE(8)
+            default:
+              BF_THROW(BEMFMM_EINVAL, "unsupported expansion order");
+          }
+#undef L2L_CASE
+          LAUNCH_OK();
+        }
+      }
       const size_t shm2 = (size_t)(ps + 64 * VecT<R>::W) * sizeof(R);
-      k_downward<R><<<T.ncell[l], 64, shm2, s>>>(p, ps, T.coff[l], T.ncell[l], l > 2 ? 1 : 0, T.cparent.p, T.ckey.p,
-                                                 Sl, T.far_ptr.p, ML.pos.p, m2l, Lx, leaf ? 1 : 0, R(1.0 / sL),
-                                                 E);
+      k_downward<R><<<T.ncell[l], 64, shm2, s>>>(p, ps, T.coff[l], T.ncell[l], l > 2 ? 1 : 0, l2l, ML.kptr.p, m2l,
+                                                 Lx, leaf ? 1 : 0, R(1.0 / sL), E);
       LAUNCH_OK();
     }
     prof_end(T, ST_L2L, s);

@@ -538,18 +538,31 @@ __global__ void k_combo_flags(const int32_t *__restrict__ order, const int2 *__r
 
 __global__ void k_combo_compact(const int32_t *__restrict__ order, const uint32_t *__restrict__ key,
                                 const int32_t *__restrict__ flag, const int32_t *__restrict__ pos, int64_t n,
-                                int32_t *__restrict__ order_k, uint32_t *__restrict__ key_k,
-                                int32_t *__restrict__ pos_k) {
+                                const int2 *__restrict__ ts, const int32_t *__restrict__ pos_t,
+                                int32_t *__restrict__ src_k, uint32_t *__restrict__ key_k,
+                                int32_t *__restrict__ dest_k) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (!flag[i]) return;
   const int32_t pair = order[i];
-  if (flag[i]) {
-    order_k[pos[i]] = pair;
-    key_k[pos[i]] = key[i];
-    pos_k[pair] = pos[i];
-  } else {
-    pos_k[pair] = -1;
-  }
+  src_k[pos[i]] = ts[pair].y;
+  key_k[pos[i]] = key[i];
+  dest_k[pos[i]] = pos_t[pair];
+}
+
+// flag of each far pair in pair order (level, target, source) from the
+// flags in offset order
+__global__ void k_flag_by_pair(const int32_t *__restrict__ order, const int32_t *__restrict__ flag, int64_t n,
+                               int32_t *__restrict__ flag_t) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag_t[order[i]] = flag[i];
+}
+
+// first kept row of every cell (CSR over all cells, rows in pair order)
+__global__ void k_kept_ptr(const int32_t *__restrict__ far_ptr, const int32_t *__restrict__ pos_t, int64_t n1,
+                           int32_t *__restrict__ kptr) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n1) kptr[c] = pos_t[far_ptr[c]];
 }
 
 __global__ void k_far_ptr(const int32_t *__restrict__ cnt_scan, int32_t C, int64_t cl, int64_t foff,
@@ -653,6 +666,68 @@ struct DevTables {
 };
 }  // namespace
 
+// Work lists of the batched L2L products: per level l >= 3, the level's
+// cells grouped by octant, cut into MFMA tiles.  Built on the host from the
+// cell keys and parents (a few tens of thousands of cells).
+static void build_l2l_lists(Tree &T, hipStream_t s) {
+  Tree::L2LList &W = T.l2lw;
+  const int L = T.L;
+  W.t0.assign(L + 2, 0);
+  W.t1.assign(L + 2, 0);
+  W.t0_64.assign(L + 2, 0);
+  W.t1_64.assign(L + 2, 0);
+  W.max_cells = 0;
+  if (L < 3) return;
+  std::vector<uint32_t> key(T.ncell_tot);
+  std::vector<int32_t> par(T.ncell_tot);
+  HIP_OK(hipMemcpyAsync(key.data(), T.ckey.p, T.ncell_tot * 4, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(par.data(), T.cparent.p, T.ncell_tot * 4, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  std::vector<int32_t> src, dest, goff, gend, tg, tr, tg64, tr64;
+  for (int l = 3; l <= L; ++l) {
+    W.t0[l] = (int64_t)tg.size();
+    W.t0_64[l] = (int64_t)tg64.size();
+    const int64_t c0 = T.coff[l], c1 = c0 + T.ncell[l];
+    for (uint32_t o = 0; o < 8; ++o) {
+      const int32_t b = (int32_t)src.size();
+      for (int64_t c = c0; c < c1; ++c)
+        if ((key[c] & 7u) == o) {
+          src.push_back(par[c]);
+          dest.push_back((int32_t)(c - c0));
+        }
+      const int32_t e = (int32_t)src.size();
+      if (e == b) continue;
+      const int32_t g = (int32_t)goff.size();
+      goff.push_back((int32_t)o);
+      gend.push_back(e);
+      for (int32_t r = b; r < e; r += M2L_ROWS32) {
+        tg.push_back(g);
+        tr.push_back(r);
+      }
+      for (int32_t r = b; r < e; r += M2L_ROWS64) {
+        tg64.push_back(g);
+        tr64.push_back(r);
+      }
+    }
+    W.t1[l] = (int64_t)tg.size();
+    W.t1_64[l] = (int64_t)tg64.size();
+    W.max_cells = std::max<int64_t>(W.max_cells, T.ncell[l]);
+  }
+  auto up = [&](DBuf<int32_t> &d, const std::vector<int32_t> &h) {
+    d.alloc(std::max<size_t>(h.size(), 1));
+    if (!h.empty()) HIP_OK(hipMemcpyAsync(d.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, s));
+  };
+  up(W.src, src);
+  up(W.dest, dest);
+  up(W.group_off, goff);
+  up(W.group_end, gend);
+  up(W.tile_group, tg);
+  up(W.tile_row, tr);
+  up(W.tile_group64, tg64);
+  up(W.tile_row64, tr64);
+  HIP_OK(hipStreamSynchronize(s));  // host vectors go out of scope
+}
+
 // Device copies of the translation operators, built once per (device, p,
 // MAC) and shared by all trees.
 void upload_tables(Tree &T, hipStream_t s) {
@@ -689,20 +764,23 @@ void upload_tables(Tree &T, hipStream_t s) {
     D->m2l64.alloc(sw64.size());
     HIP_OK(hipMemcpyAsync(D->m2l32.p, sw32.data(), sw32.size() * 4, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(D->m2l64.p, sw64.data(), sw64.size() * 8, hipMemcpyHostToDevice, s));
-    // M2M / L2L stored transposed, [oct][in][out], so that lanes of a wave
-    // (one output coefficient each) read consecutive words
-    std::vector<double> a((size_t)8 * ps * ps), b(a.size());
+    // M2M stored transposed, [oct][in][out], so that lanes of a wave (one
+    // output coefficient each) read consecutive words; L2L in the MFMA
+    // B-operand order of the M2L tables, one per octant
+    std::vector<double> a((size_t)8 * ps * ps), b((size_t)8 * KK * NT * 64);
     for (int o = 0; o < 8; ++o)
       for (int r = 0; r < ps; ++r)
-        for (int c = 0; c < ps; ++c) {
-          a[((size_t)o * ps + c) * ps + r] = tb.m2m[((size_t)o * ps + r) * ps + c];
-          b[((size_t)o * ps + c) * ps + r] = tb.l2l[((size_t)o * ps + r) * ps + c];
-        }
+        for (int c = 0; c < ps; ++c) a[((size_t)o * ps + c) * ps + r] = tb.m2m[((size_t)o * ps + r) * ps + c];
+    for (int o = 0; o < 8; ++o)
+      for (int kk = 0; kk < KK; ++kk)
+        for (int ct = 0; ct < NT; ++ct)
+          for (int l = 0; l < 64; ++l) {
+            const int out = ct * 16 + (l % 16), in = (l / 16) * KK + kk;
+            b[(((size_t)o * KK + kk) * NT + ct) * 64 + l] = tb.l2l[((size_t)o * ps + out) * ps + in];
+          }
     std::vector<float> a32(a.size()), b32(b.size());
-    for (size_t i = 0; i < a.size(); ++i) {
-      a32[i] = (float)a[i];
-      b32[i] = (float)b[i];
-    }
+    for (size_t i = 0; i < a.size(); ++i) a32[i] = (float)a[i];
+    for (size_t i = 0; i < b.size(); ++i) b32[i] = (float)b[i];
     D->m2m32.alloc(a32.size());
     D->l2l32.alloc(b32.size());
     D->m2m64.alloc(a.size());
@@ -1034,11 +1112,14 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     int nbits = 1;
     while ((1 << nbits) < T.tab->noff()) ++nbits;
     radix_sort_u32(key.p, order.p, nf, nbits, s);
-    DBuf<int32_t> flag, pos;
+    DBuf<int32_t> flag, pos, flag_t, pos_t;
     DBuf<uint32_t> ckeyc;
     flag.alloc(nf);
     pos.alloc(nf);
+    flag_t.alloc(nf + 1);
+    pos_t.alloc(nf + 1);
     ckeyc.alloc(nf);
+    const int64_t CT1 = T.ncell_tot + 1;
     for (int combo = 0; combo < 3; ++combo) {
       Tree::M2LList &ML = T.m2l[combo];
       k_combo_flags<<<cdiv(nf, TB), TB, 0, s>>>(order.p, T.far_ts.p, T.crange.p, nf, combo, flag.p);
@@ -1046,9 +1127,18 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
       int32_t nk = 0;
       exclusive_scan_i32(flag.p, pos.p, nf, s, &nk);
       ML.n = nk;
-      ML.order.alloc(std::max<int32_t>(nk, 1));
-      ML.pos.alloc(nf);
-      k_combo_compact<<<cdiv(nf, TB), TB, 0, s>>>(order.p, key.p, flag.p, pos.p, nf, ML.order.p, ckeyc.p, ML.pos.p);
+      // output rows in pair order: a cell's rows are contiguous
+      k_flag_by_pair<<<cdiv(nf, TB), TB, 0, s>>>(order.p, flag.p, nf, flag_t.p);
+      LAUNCH_OK();
+      HIP_OK(hipMemsetAsync(flag_t.p + nf, 0, 4, s));
+      exclusive_scan_i32(flag_t.p, pos_t.p, nf + 1, s, nullptr);
+      ML.kptr.alloc(CT1);
+      k_kept_ptr<<<cdiv(CT1, TB), TB, 0, s>>>(T.far_ptr.p, pos_t.p, CT1, ML.kptr.p);
+      LAUNCH_OK();
+      ML.src.alloc(std::max<int32_t>(nk, 1));
+      ML.dest.alloc(std::max<int32_t>(nk, 1));
+      k_combo_compact<<<cdiv(nf, TB), TB, 0, s>>>(order.p, key.p, flag.p, pos.p, nf, T.far_ts.p, pos_t.p, ML.src.p,
+                                                  ckeyc.p, ML.dest.p);
       LAUNCH_OK();
       if (nk == 0) continue;
       DBuf<int32_t> gflag, gpos, gbeg;
@@ -1084,6 +1174,8 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
       }
     }
   }
+
+  build_l2l_lists(T, s);
 
   // leaf membership, inverse permutations, sorted point data
   const int64_t CL = T.ncell[L];
