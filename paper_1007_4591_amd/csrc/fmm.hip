@@ -513,8 +513,8 @@ __global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int6
 // -grad).  Dipole m: lp += m.d/r^3, (lx,ly,lz) += 3 (m.d) d/r^5 - m/r^3 (=
 // -grad).  d = target - source, ri = 1/r (0 for the excluded self pair).
 template <class R, int SRC, int OUT>
-__device__ __forceinline__ void pair_accumulate(const typename V4<R>::T &s4, const typename V4<R>::T *sdip, int j,
-                                                R dx, R dy, R dz, R ri, R &lp, R &lx, R &ly, R &lz) {
+__device__ __forceinline__ void pair_eval(const typename V4<R>::T &s4, const typename V4<R>::T &m4, R dx, R dy, R dz,
+                                          R ri, R &lp, R &lx, R &ly, R &lz) {
   if (SRC == SRC_PANEL_MONO || SRC == SRC_CHARGE_MONO) {
     const R wr = s4.w * ri;
     if (OUT == OUT_POT || OUT == OUT_POTGRAD) lp += wr;
@@ -525,7 +525,6 @@ __device__ __forceinline__ void pair_accumulate(const typename V4<R>::T &s4, con
       lz += t * dz;
     }
   } else {
-    const typename V4<R>::T m4 = sdip[j];
     const R ri2 = ri * ri;
     const R ri3 = ri2 * ri;
     const R md = m4.x * dx + m4.y * dy + m4.z * dz;
@@ -543,6 +542,14 @@ __device__ __forceinline__ void pair_accumulate(const typename V4<R>::T &s4, con
       lz += t * dz - m4.z * ri3;
     }
   }
+}
+
+template <class R, int SRC, int OUT>
+__device__ __forceinline__ void pair_accumulate(const typename V4<R>::T &s4, const typename V4<R>::T *sdip, int j,
+                                                R dx, R dy, R dz, R ri, R &lp, R &lx, R &ly, R &lz) {
+  typename V4<R>::T m4{};
+  if (SRC == SRC_PANEL_DIP || SRC == SRC_PANEL_MONODIP) m4 = sdip[j];
+  pair_eval<R, SRC, OUT>(s4, m4, dx, dy, dz, ri, lp, lx, ly, lz);
 }
 
 struct P2PArgs {
@@ -621,8 +628,47 @@ __global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
           pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
         }
       } else {
-#pragma unroll 4
-        for (int j = sb; j < se; ++j) {
+        // software pipelined: the records of the next PF sources are
+        // requested before the current PF are evaluated, so the wait for
+        // the scalar loads falls after the arithmetic
+        constexpr int PF = 4;
+        constexpr bool DIPS = SRC == SRC_PANEL_DIP || SRC == SRC_PANEL_MONODIP;
+        int j = sb;
+        if (se - sb >= 2 * PF) {
+          R4 cs[PF], cm[PF];
+#pragma unroll
+          for (int u = 0; u < PF; ++u) {
+            cs[u] = spos[j + u];
+            if (DIPS) cm[u] = sdip[j + u];
+          }
+          for (; j + 2 * PF <= se; j += PF) {
+            R4 ns[PF], nm[PF];
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+              ns[u] = spos[j + PF + u];
+              if (DIPS) nm[u] = sdip[j + PF + u];
+            }
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+              const R dx = ux - cs[u].x, dy = uy - cs[u].y, dz = uz - cs[u].z;
+              const R r2 = dx * dx + dy * dy + dz * dz;
+              pair_eval<R, SRC, OUT>(cs[u], cm[u], dx, dy, dz, rsq(r2), lp, lx, ly, lz);
+            }
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+              cs[u] = ns[u];
+              if (DIPS) cm[u] = nm[u];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < PF; ++u) {
+            const R dx = ux - cs[u].x, dy = uy - cs[u].y, dz = uz - cs[u].z;
+            const R r2 = dx * dx + dy * dy + dz * dz;
+            pair_eval<R, SRC, OUT>(cs[u], cm[u], dx, dy, dz, rsq(r2), lp, lx, ly, lz);
+          }
+          j += PF;
+        }
+        for (; j < se; ++j) {
           const R4 s4 = spos[j];
           const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
           const R r2 = dx * dx + dy * dy + dz * dz;
@@ -950,13 +996,15 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   a.dbg_far = B.dbg_far.p;
   a.near_out = B.near_out.p;
   B.last_tgt = rq.tgt;
+  // The near field runs on the second stream beside P2M-M2M: those passes
+  // leave most of the chip idle (few cells per level, LDS-bound P2M).
+  const hipStream_t ss = T.concurrent ? T.side_stream : s;
   if (nchunks > 0) {
-    // The near field runs on the second stream beside P2P-M2M: those passes
-    // leave most of the chip idle (few cells per level, LDS-bound P2M).
-    const hipStream_t ss = T.concurrent ? T.side_stream : s;
     HIP_OK(hipStreamWaitEvent(ss, T.ev_fork, 0));
+    const P2PArgs &ap = a;
+    const unsigned nb = (unsigned)nchunks;
     prof_begin(T, ST_P2P, ss);
-#define P2P_CALL(S, Tg, O) k_p2p_near<R, S, Tg, O><<<nchunks, 64, 0, ss>>>(a)
+#define P2P_CALL(S, Tg, O) k_p2p_near<R, S, Tg, O><<<nb, 64, 0, ss>>>(ap)
     if (!tgt_ch) {
       if (rq.src == SRC_PANEL_MONO && rq.out == OUT_NGRAD) P2P_CALL(SRC_PANEL_MONO, TGT_PANEL, OUT_NGRAD);
       else if (rq.src == SRC_PANEL_DIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_DIP, TGT_PANEL, OUT_POT);
