@@ -224,10 +224,15 @@ int bemfmm_debug_expansions(bemfmm_tree *tree, int precision, int which, double 
  * targets the potential.  near_host, far_host: [n_targets]. */
 int bemfmm_debug_fields(bemfmm_tree *tree, int precision, double *near_host, double *far_host);
 
-/* Per-stage device time of matvecs since the last reset, from HIP events on
- * the stream (enable = 1 starts recording, 0 stops; reset clears).  stage
- * names: "p2m", "m2m", "m2l", "l2l", "p2p" (includes L2P and the final
- * combination), "other".  ms_host and count_host receive totals. */
+/* Per-stage device time of FMM products since the last reset, from HIP
+ * events recorded on the stream that runs each stage (enable = 1 starts
+ * recording, 0 stops; reset clears).  Stage names: "p2m", "m2m", "m2l",
+ * "l2l" (downward pass incl. the batched L2L), "p2p" (near field, on the
+ * second stream), "l2p" (far-field evaluation and final combination),
+ * "other" (packing of the inputs).  A name alone sums every product; "name/op/
+ * precision" (e.g. "p2p/0/1") restricts it to one operator (BEMFMM_OP_*) at
+ * one precision (BEMFMM_FP64 = 0, BEMFMM_FP32 = 1).  ms_host and
+ * count_host receive the total time and the number of stage instances. */
 int bemfmm_profile(bemfmm_tree *tree, int enable, int reset);
 int bemfmm_profile_get(bemfmm_tree *tree, const char *stage, double *ms_host, int64_t *count_host);
 

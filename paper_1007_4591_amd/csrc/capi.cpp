@@ -2,6 +2,7 @@
 // No C++ exception crosses this boundary.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 
@@ -240,23 +241,45 @@ int bemfmm_profile(bemfmm_tree *tree, int enable, int reset) {
     Tree *T = check_tree(tree);
     T->prof = enable != 0;
     if (reset)
-      for (int i = 0; i < 7; ++i) {
-        T->prof_ms[i] = 0;
-        T->prof_cnt[i] = 0;
-      }
+      for (auto &k : T->prof_ms)
+        for (auto &pr : k)
+          for (auto &v : pr) v = 0;
+    if (reset)
+      for (auto &k : T->prof_cnt)
+        for (auto &pr : k)
+          for (auto &v : pr) v = 0;
   });
 }
 
 int bemfmm_profile_get(bemfmm_tree *tree, const char *stage, double *ms_host, int64_t *count_host) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    need(stage != nullptr, "stage is NULL");
     static const char *names[7] = {"p2m", "m2m", "m2l", "l2l", "p2p", "other", "l2p"};
+    // "name" (every product) or "name/op/precision" (one operator, FP64 = 0 or FP32 = 1)
+    const std::string sname(stage);
+    const size_t slash = sname.find('/');
+    const std::string base = sname.substr(0, slash);
     int k = -1;
     for (int i = 0; i < 7; ++i)
-      if (stage && std::strcmp(stage, names[i]) == 0) k = i;
+      if (base == names[i]) k = i;
     need(k >= 0, "unknown stage");
-    if (ms_host) *ms_host = T->prof_ms[k];
-    if (count_host) *count_host = T->prof_cnt[k];
+    int op = -1, prec = -1;
+    if (slash != std::string::npos) {
+      need(std::sscanf(sname.c_str() + slash, "/%d/%d", &op, &prec) == 2 && op >= 0 && op < 6 &&
+               (prec == 0 || prec == 1),
+           "stage filter must be name/op/precision with op 0..5 and precision 0 or 1");
+    }
+    double ms = 0;
+    int64_t cnt = 0;
+    for (int kind = 0; kind < 7; ++kind)
+      for (int pr = 0; pr < 2; ++pr) {
+        if (op >= 0 && (kind != op || pr != prec)) continue;
+        ms += T->prof_ms[kind][pr][k];
+        cnt += T->prof_cnt[kind][pr][k];
+      }
+    if (ms_host) *ms_host = ms;
+    if (count_host) *count_host = cnt;
   });
 }
 

@@ -232,9 +232,11 @@ struct Tree {
   bool concurrent = true;        // near field on the second stream
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool prof = false;
-  double prof_ms[7] = {0, 0, 0, 0, 0, 0, 0};
-  int64_t prof_cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+  // stage times per [product kind: the six operators, then any other][FP64, FP32][stage]
+  double prof_ms[7][2][7] = {};
+  int64_t prof_cnt[7][2][7] = {};
   bool prof_pending[7] = {false, false, false, false, false, false, false};
+  int prof_kind = 6, prof_prec = 0;  // product being timed
   hipEvent_t ev[14] = {};
   bool ev_init = false;
 
@@ -273,6 +275,7 @@ struct FmmRequest {
   bool area_scale;
   double *y;            // OUT_POT/NGRAD: [n_targets]; OUT_POTGRAD: [n_targets*4] (pot, gx, gy, gz)
   bool accumulate;      // y += instead of y =
+  int op = -1;          // BEMFMM_OP_* this request implements (-1: another product), for stage timing
 };
 
 void fmm_apply(Tree &T, int precision, const FmmRequest &rq, hipStream_t s);

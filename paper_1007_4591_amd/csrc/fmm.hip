@@ -874,8 +874,8 @@ static void prof_collect(Tree &T) {
     HIP_OK(hipEventSynchronize(T.ev[2 * st + 1]));
     float ms = 0.f;
     HIP_OK(hipEventElapsedTime(&ms, T.ev[2 * st], T.ev[2 * st + 1]));
-    T.prof_ms[st] += ms;
-    T.prof_cnt[st] += 1;
+    T.prof_ms[T.prof_kind][T.prof_prec][st] += ms;
+    T.prof_cnt[T.prof_kind][T.prof_prec][st] += 1;
     T.prof_pending[st] = false;
   }
 }
@@ -1149,6 +1149,8 @@ void fmm_apply(Tree &T, int precision, const FmmRequest &rq, hipStream_t s) {
     T.ev_init = true;
     if (const char *e = getenv("BEMFMM_CONCURRENT_P2P")) T.concurrent = atoi(e) != 0;
   }
+  T.prof_kind = (rq.op >= 0 && rq.op < 6) ? rq.op : 6;
+  T.prof_prec = prec == BEMFMM_FP64 ? 0 : 1;
   if (prec == BEMFMM_FP64)
     run_fmm<double>(T, B, rq, s);
   else

@@ -339,6 +339,7 @@ void op_apply(Tree &T, int op, int precision, const double *x, double *y, hipStr
     default:
       BF_THROW(BEMFMM_EINVAL, "unknown operator");
   }
+  r.op = op;
   const bool to_charges = (op == BEMFMM_OP_BT || op == BEMFMM_OP_C);
   const bool from_charges = (op == BEMFMM_OP_B || op == BEMFMM_OP_CT);
   if ((to_charges || from_charges) && T.Q == 0) {
