@@ -247,6 +247,17 @@ __global__ void __launch_bounds__(64) k_m2m(int np2, int ps, int64_t c0, int64_t
 
 // -------------------------------------------------------------------- M2L
 
+// Workgroups are dispatched to the 8 XCDs of the chip in turn, and each XCD
+// has its own L2.  This maps launch order to work order so that XCD x runs
+// the x-th contiguous eighth of the work items: neighbouring chunks (which
+// share most of their near-field sources) then meet in the same L2.
+__device__ __forceinline__ int xcd_block(int bid, int n) {
+  constexpr int NX = 8;
+  const int q = n / NX, r = n - q * NX;
+  const int x = bid % NX, k = bid / NX;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // Offset-grouped dense M2L on MFMA.  A work tile is 4 waves x RT x 16
 // consecutive pairs of one offset group (pairs are sorted by offset, all
 // levels together: the scaled operator depends on the offset only).  Each
@@ -258,6 +269,8 @@ __global__ void __launch_bounds__(64) k_m2m(int np2, int ps, int64_t c0, int64_t
 // source row: at k-step kk, lane group g = lane/16 supplies input g*KK + kk
 // (the B table is stored in that order).  Rows past the end of the group
 // repeat its last row (MFMA rows are independent; they are not stored).
+// USE only names the instance (0: M2L, 1: the batched L2L), so that
+// profiles tell the two apart.
 // Registers are budgeted for two waves per SIMD so that one wave's gather
 // overlaps the other's MFMA work.  With BLDS the four waves of a tile share
 // the operator through LDS instead of each reading it from L2.
@@ -265,7 +278,7 @@ __global__ void __launch_bounds__(64) k_m2m(int np2, int ps, int64_t c0, int64_t
 // so that the downward pass reads a cell's rows as one contiguous run.  Output layouts (checked on the device): FP32 16x16x4 puts
 // D[4*(lane/16) + q][lane%16] in register q; FP64 16x16x4 puts
 // D[lane/16 + 4*q][lane%16] in register q.
-template <class R, int NT, int RT, bool BLDS>
+template <class R, int NT, int RT, bool BLDS, int USE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_m2l(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ tile_row,
       const int32_t *__restrict__ group_off, const int32_t *__restrict__ group_end, const int32_t *__restrict__ src,
@@ -279,7 +292,7 @@ k_m2l(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ tile_r
   using Acc = typename std::conditional<F64, f64x4, f32x4>::type;
   __shared__ V16 Bs[BLDS ? TB / W : 1];
   __shared__ int Ds[BLDS ? 4 * 16 * RT : 1];
-  const int tile = blockIdx.x;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);  // tiles of one group share an L2
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = tile_group[tile];
   const int end = group_end[g];
@@ -587,7 +600,8 @@ template <class R, int SRC, int TGT, int OUT>
 __global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
   using R4 = typename V4<R>::T;
   __shared__ R red[4][64];
-  const int4 ch = a.chunks[blockIdx.x];  // (leaf, first target, count, groups)
+  // (leaf, first target, count, groups); chunks are in Morton order
+  const int4 ch = a.chunks[xcd_block(blockIdx.x, gridDim.x)];
   const int leaf = ch.x, count = ch.z, G = ch.w;
   const int lane = threadIdx.x;
   const int g = lane / count, tl = lane - g * count;
@@ -1048,11 +1062,11 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
 #define M2L_CASE(nt)                                                                                           \
   case nt:                                                                                                     \
     if (f64)                                                                                                   \
-      k_m2l<double, nt, M2L_RT64, false><<<dim3((unsigned)ML.ntiles64), 256, 0, s>>>(                         \
+      k_m2l<double, nt, M2L_RT64, false, 0><<<dim3((unsigned)ML.ntiles64), 256, 0, s>>>(                         \
           ML.tile_group64.p, ML.tile_row64.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p, T.t_m2l64,             \
           reinterpret_cast<const double *>(M), reinterpret_cast<double *>(m2l));                               \
     else                                                                                                       \
-      k_m2l<float, nt, M2L_RT32, true><<<dim3((unsigned)ML.ntiles), 256, 0, s>>>(                              \
+      k_m2l<float, nt, M2L_RT32, true, 0><<<dim3((unsigned)ML.ntiles), 256, 0, s>>>(                              \
           ML.tile_group.p, ML.tile_row.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p, T.t_m2l32,                 \
           reinterpret_cast<const float *>(M), reinterpret_cast<float *>(m2l));                                 \
     break;
@@ -1085,11 +1099,11 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
 #define L2L_CASE(nt)                                                                                           \
   case nt:                                                                                                     \
     if (f64)                                                                                                   \
-      k_m2l<double, nt, M2L_RT64, false><<<dim3((unsigned)(t1 - t0)), 256, 0, s>>>(                           \
+      k_m2l<double, nt, M2L_RT64, false, 1><<<dim3((unsigned)(t1 - t0)), 256, 0, s>>>(                           \
           LW.tile_group64.p + t0, LW.tile_row64.p + t0, LW.group_off.p, LW.group_end.p, LW.src.p, LW.dest.p,   \
           T.t_l2l64, reinterpret_cast<const double *>(Lx), reinterpret_cast<double *>(l2l));                   \
     else                                                                                                       \
-      k_m2l<float, nt, M2L_RT32, true><<<dim3((unsigned)(t1 - t0)), 256, 0, s>>>(                              \
+      k_m2l<float, nt, M2L_RT32, true, 1><<<dim3((unsigned)(t1 - t0)), 256, 0, s>>>(                              \
           LW.tile_group.p + t0, LW.tile_row.p + t0, LW.group_off.p, LW.group_end.p, LW.src.p, LW.dest.p,       \
           T.t_l2l32, reinterpret_cast<const float *>(Lx), reinterpret_cast<float *>(l2l));                     \
     break;
