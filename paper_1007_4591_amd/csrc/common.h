@@ -230,6 +230,8 @@ struct Tree {
   // events; stage profiling events
   hipStream_t side_stream = nullptr;
   bool concurrent = true;        // near field on the second stream
+  bool m2l_persistent = true;    // FP32 M2L: persistent workgroups (else one tile per workgroup)
+  int n_cu = 256;                // compute units of the device
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool prof = false;
   // stage times per [product kind: the six operators, then any other][FP64, FP32][stage]

@@ -380,6 +380,127 @@ k_m2l(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ tile_r
     }
 }
 
+// Persistent FP32 M2L.  A workgroup (4 waves, one per SIMD) walks a
+// contiguous range of tiles; the ranges are XCD-aware, so the ranges of one
+// XCD are adjacent and consecutive tiles mostly share their offset group.
+// The operator is reloaded into LDS only when the offset group changes
+// (about once per nine tiles, instead of once per tile).  Two workgroups
+// share a CU and drift out of step, so one's loads overlap the other's MFMA
+// work; one tile per workgroup kept the two in lock step (gather, then
+// products, then stores at the same time) and overlapped little.  The
+// arithmetic per tile is that of k_m2l (same operand layouts, same K order),
+// so results are identical.
+template <int NT, int RT>
+__device__ __forceinline__ void m2l_tiles(const int32_t *__restrict__ tile_group,
+                                          const int32_t *__restrict__ tile_row,
+                                          const int32_t *__restrict__ group_off,
+                                          const int32_t *__restrict__ group_end,
+                                          const int32_t *__restrict__ src, const int32_t *__restrict__ dest,
+                                          const float *__restrict__ Tsw, const float *__restrict__ M,
+                                          float *__restrict__ out, int ntiles, float4 *Bs) {
+  constexpr int PS = NT * 16;
+  constexpr int KK = PS / 4;
+  constexpr int TB4 = KK * NT * 16;          // float4 per operator
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int nwg = gridDim.x;
+  const int wg = xcd_block(blockIdx.x, nwg);
+  const int t0 = (int)((int64_t)ntiles * wg / nwg), t1 = (int)((int64_t)ntiles * (wg + 1) / nwg);
+  if (t0 >= t1) return;  // uniform over the workgroup
+
+  struct TileIn {
+    int g, end, row0;
+  };
+  auto tile_in = [&](int t) {
+    TileIn s;
+    s.g = tile_group[t];
+    s.end = group_end[s.g];
+    s.row0 = tile_row[t] + wave * (16 * RT);
+    return s;
+  };
+  auto load_a = [&](const TileIn &s, float (&a)[RT][KK], int (&d)[RT][4]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int sr = src[min(s.row0 + rt * 16 + i16, s.end - 1)];
+      const float4 *Ms = reinterpret_cast<const float4 *>(M + (size_t)sr * PS + kq * KK);
+#pragma unroll
+      for (int v = 0; v < KK / 4; ++v) {
+        const float4 q = Ms[v];
+        a[rt][4 * v] = q.x;
+        a[rt][4 * v + 1] = q.y;
+        a[rt][4 * v + 2] = q.z;
+        a[rt][4 * v + 3] = q.w;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rr = min(s.row0 + rt * 16 + 4 * kq + q, s.end - 1);
+        d[rt][q] = dest[rr];
+      }
+    }
+  };
+  auto products = [&](const TileIn &s, const float (&a)[RT][KK], const int (&d)[RT][4], const float4 *Bsrc) {
+    if (s.row0 >= s.end) return;
+    f32x4 acc[RT][NT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const float *B = reinterpret_cast<const float *>(Bsrc) + lane;
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) {
+        const float b = B[(kk * NT + ct) * 64];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][kk], b, acc[rt][ct], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (s.row0 + rt * 16 + 4 * kq + q < s.end) {
+          float *o = out + (size_t)d[rt][q] * PS + i16;
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct) o[ct * 16] = acc[rt][ct][q];
+        }
+  };
+  auto stage_b = [&](int g, float4 *dst) {
+    const float4 *Bg = reinterpret_cast<const float4 *>(Tsw) + (size_t)group_off[g] * TB4;
+    for (int v = threadIdx.x; v < TB4; v += 256) dst[v] = Bg[v];
+  };
+
+  float a[RT][KK];
+  int d[RT][4];
+  TileIn cur = tile_in(t0);
+  stage_b(cur.g, Bs);
+  __syncthreads();
+  for (int t = t0; t < t1; ++t) {
+    if (t > t0) {
+      const TileIn nxt = tile_in(t);
+      if (group_off[nxt.g] != group_off[cur.g]) {
+        __syncthreads();  // every wave is done with the current operator
+        stage_b(nxt.g, Bs);
+        __syncthreads();
+      }
+      cur = nxt;
+    }
+    load_a(cur, a, d);
+    products(cur, a, d, Bs);
+  }
+}
+
+template <int NT, int RT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_m2l_pers(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ tile_row,
+           const int32_t *__restrict__ group_off, const int32_t *__restrict__ group_end,
+           const int32_t *__restrict__ src, const int32_t *__restrict__ dest, const float *__restrict__ Tsw,
+           const float *__restrict__ M, float *__restrict__ out, int ntiles) {
+  __shared__ float4 Bs[NT * 4 * NT * 16];
+  m2l_tiles<NT, RT>(tile_group, tile_row, group_off, group_end, src, dest, Tsw, M, out, ntiles, Bs);
+}
+
 // ----------------------------------------------------------- downward pass
 
 template <class R> struct VecT;
@@ -1065,6 +1186,10 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
       k_m2l<double, nt, M2L_RT64, false, 0><<<dim3((unsigned)ML.ntiles64), 256, 0, s>>>(                         \
           ML.tile_group64.p, ML.tile_row64.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p, T.t_m2l64,             \
           reinterpret_cast<const double *>(M), reinterpret_cast<double *>(m2l));                               \
+    else if (T.m2l_persistent)                                                                                  \
+      k_m2l_pers<nt, M2L_RT32><<<dim3((unsigned)std::min<int64_t>(ML.ntiles, 2 * T.n_cu)), 256, 0, s>>>(      \
+          ML.tile_group.p, ML.tile_row.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p, T.t_m2l32,      \
+          reinterpret_cast<const float *>(M), reinterpret_cast<float *>(m2l), (int)ML.ntiles);                 \
     else                                                                                                       \
       k_m2l<float, nt, M2L_RT32, true, 0><<<dim3((unsigned)ML.ntiles), 256, 0, s>>>(                              \
           ML.tile_group.p, ML.tile_row.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p, T.t_m2l32,                 \
@@ -1162,6 +1287,10 @@ void fmm_apply(Tree &T, int precision, const FmmRequest &rq, hipStream_t s) {
     HIP_OK(hipStreamCreateWithFlags(&T.side_stream, hipStreamNonBlocking));  // default priority
     T.ev_init = true;
     if (const char *e = getenv("BEMFMM_CONCURRENT_P2P")) T.concurrent = atoi(e) != 0;
+    if (const char *e = getenv("BEMFMM_M2L_PERSISTENT")) T.m2l_persistent = atoi(e) != 0;
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&T.n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   }
   T.prof_kind = (rq.op >= 0 && rq.op < 6) ? rq.op : 6;
   T.prof_prec = prec == BEMFMM_FP64 ? 0 : 1;
