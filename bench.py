@@ -174,9 +174,9 @@ def main():
                 "avg_ms": p2p_ms, "launches": live["p2p"][1], "traffic": pmc_traffic("k_p2p_near<float, 0, 0, 1>")}
     roof_p2p["frac"] = roof_p2p["achieved"] / roof_p2p["peak"]
     roof_p2p["frac_of_packed_peak"] = roof_p2p["achieved"] / (PEAK_FP32_PACKED / 1e12)
-    roof_m2l = {"bound": "mfma", "kernel": "k_m2l<float,7,4,true> (M2L, FP32 MFMA)",
+    roof_m2l = {"bound": "mfma", "kernel": "k_m2l_pers<7,4> (M2L, FP32 MFMA, persistent)",
                 "achieved": m2l_flops / (m2l_ms / 1e3) / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                "avg_ms": m2l_ms, "launches": live["m2l"][1], "traffic": pmc_traffic("k_m2l<float, 7, 4, true>")}
+                "avg_ms": m2l_ms, "launches": live["m2l"][1], "traffic": pmc_traffic("k_m2l_pers<7, 4>")}
     roof_m2l["frac"] = roof_m2l["achieved"] / roof_m2l["peak"]
     roofline = roof_p2p if p2p_ms >= m2l_ms else roof_m2l
     print(f"[bench] stages(ms, count)={stages}", file=sys.stderr, flush=True)

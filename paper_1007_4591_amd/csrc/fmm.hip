@@ -58,7 +58,14 @@ template <> __device__ inline float hinv<float>(int m) { return c_half_inv_m_f[m
 template <> __device__ inline double hinv<double>(int m) { return c_half_inv_m_d[m]; }
 
 __device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ inline double rsq(double x) { return rsqrt(x); }
+// 1/sqrt(x) in FP64: the hardware estimate refined by one Newton step for
+// x^(-1/2), y <- y + y (1 - x y^2) / 2.  Arguments are positive: the only
+// zero (the excluded self pair) is discarded by index after the call.
+__device__ inline double rsq(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = __builtin_fma(-x * y, y, 1.0);
+  return __builtin_fma(0.5 * y, e, y);
+}
 
 // Regular solid harmonics R_n^m(x, y, z) for 0 <= m <= n < p, generated in
 // m-major order by the recurrences documented with the host tables; calls
