@@ -83,8 +83,18 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(const int32_t *in, in
 
 }  // namespace
 
+namespace {
+// total of a scan from its block sums
+__global__ void k_scan_total(const int32_t *__restrict__ sums, const int32_t *__restrict__ sums_scan, int nb,
+                             int32_t *__restrict__ tot) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *tot = nb > 1 ? sums_scan[nb - 1] + sums[nb - 1] : sums[0];
+}
+}  // namespace
+
 // Exclusive prefix sum of n int32 values (out may alias in); the total is
-// returned through total_host when non-NULL (synchronises the stream).
+// returned through total_host when non-NULL (one stream synchronisation).
+// Without a total nothing waits: temporary buffers go back to the caching
+// allocator, which synchronises before it reuses them.
 void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, int32_t *total_host) {
   if (n <= 0) {
     if (total_host) *total_host = 0;
@@ -99,18 +109,13 @@ void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t 
     sums_scan.alloc(nb + 1);
     exclusive_scan_i32(sums.p, sums_scan.p, nb, s, nullptr);
   }
-  int32_t last_in = 0;
-  if (total_host) HIP_OK(hipMemcpyAsync(&last_in, in + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  if (total_host) HIP_OK(hipStreamSynchronize(s));
   k_scan_apply<<<nb, SCAN_BLOCK, 0, s>>>(in, n, nb > 1 ? sums_scan.p : nullptr, out);
   LAUNCH_OK();
   if (total_host) {
-    int32_t last_out = 0;
-    HIP_OK(hipMemcpyAsync(&last_out, out + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    k_scan_total<<<1, 1, 0, s>>>(sums.p, nb > 1 ? sums_scan.p : nullptr, nb, sums.p + nb);
+    LAUNCH_OK();
+    HIP_OK(hipMemcpyAsync(total_host, sums.p + nb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    *total_host = last_out + last_in;
-  } else {
-    HIP_OK(hipStreamSynchronize(s));  // sums buffers are freed on return
   }
 }
 
@@ -198,7 +203,6 @@ void radix_sort_u32(uint32_t *keys, int32_t *vals, int64_t n, int bits, hipStrea
     HIP_OK(hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     HIP_OK(hipMemcpyAsync(vals, va, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   }
-  HIP_OK(hipStreamSynchronize(s));
 }
 
 namespace {
@@ -426,38 +430,73 @@ __device__ inline bool mac_far_dev(int ox, int oy, int oz, double theta2, int ma
 // Lists at level l (l >= 1): candidates are the children of the near cells
 // of the target's parent; the MAC splits them into near and far.  Pass 1
 // counts (fill == 0), pass 2 writes.
-__global__ void k_lists(int32_t C, int64_t cl, int64_t cpl, const int32_t *__restrict__ parent_g,
-                        const int32_t *__restrict__ xyz, const int2 *__restrict__ child,
-                        const int32_t *__restrict__ pnear_ptr, const int32_t *__restrict__ pnear_idx,
-                        double theta2, int mac, int fill, int32_t *__restrict__ near_cnt,
-                        int32_t *__restrict__ far_cnt, const int32_t *__restrict__ near_ptr,
-                        int32_t *__restrict__ near_idx, const int32_t *__restrict__ far_ptr,
-                        int2 *__restrict__ far_ts) {
-  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// Near and far lists of the cells of level l (level-local index t), one wave
+// per cell.  The candidates are the children of the parent's near cells, in
+// increasing order (the parent's near list is increasing, and child ranges
+// are increasing and disjoint).  Lane k takes the k-th parent-near entry of
+// each run of 64 and classifies its children (at most 8); a prefix sum over
+// the lanes gives each lane its place, so both lists keep candidate order.
+// fill = 0 counts, fill = 1 writes at near_ptr / far_ptr.
+__global__ void __launch_bounds__(64) k_lists(int32_t C, int64_t cl, int64_t cpl, const int32_t *__restrict__ parent_g,
+                                              const int32_t *__restrict__ xyz, const int2 *__restrict__ child,
+                                              const int32_t *__restrict__ pnear_ptr,
+                                              const int32_t *__restrict__ pnear_idx, double theta2, int mac,
+                                              int fill, int32_t *__restrict__ near_cnt, int32_t *__restrict__ far_cnt,
+                                              const int32_t *__restrict__ near_ptr, int32_t *__restrict__ near_idx,
+                                              const int32_t *__restrict__ far_ptr, int2 *__restrict__ far_ts) {
+  const int32_t t = blockIdx.x;
   if (t >= C) return;
+  const int lane = threadIdx.x;
   int tx, ty, tz;
   unpack_xyz(xyz[cl + t], tx, ty, tz);
-  int32_t P = parent_g[cl + t] - (int32_t)cpl;  // level-local parent
-  int32_t nn = 0, nf = 0;
-  int32_t nbase = fill ? near_ptr[t] : 0;
-  int32_t fbase = fill ? far_ptr[t] : 0;
-  for (int32_t e = pnear_ptr[P]; e < pnear_ptr[P + 1]; ++e) {
-    int32_t sp = pnear_idx[e];                     // level-local at l-1
-    int2 ch = child[cpl + sp];                     // global child range
-    for (int32_t sg = ch.x; sg < ch.y; ++sg) {
-      int sx, sy, sz;
-      unpack_xyz(xyz[sg], sx, sy, sz);
-      int32_t s = sg - (int32_t)cl;
-      if (mac_far_dev(sx - tx, sy - ty, sz - tz, theta2, mac)) {
-        if (fill) far_ts[fbase + nf] = make_int2((int)(cl + t), (int)sg);
-        ++nf;
-      } else {
-        if (fill) near_idx[nbase + nn] = s;
-        ++nn;
+  const int32_t P = parent_g[cl + t] - (int32_t)cpl;  // level-local parent
+  int32_t nn = 0, nf = 0;                              // running totals (uniform)
+  const int32_t nbase = fill ? near_ptr[t] : 0;
+  const int32_t fbase = fill ? far_ptr[t] : 0;
+  const int32_t e0 = pnear_ptr[P], e1 = pnear_ptr[P + 1];
+  for (int32_t eb = e0; eb < e1; eb += 64) {
+    const int32_t e = eb + lane;
+    int my_n = 0, my_f = 0;
+    unsigned farmask = 0;
+    int2 ch = make_int2(0, 0);
+    if (e < e1) {
+      ch = child[cpl + pnear_idx[e]];  // global child range
+      for (int32_t sg = ch.x; sg < ch.y; ++sg) {
+        int sx, sy, sz;
+        unpack_xyz(xyz[sg], sx, sy, sz);
+        if (mac_far_dev(sx - tx, sy - ty, sz - tz, theta2, mac)) {
+          farmask |= 1u << (sg - ch.x);
+          ++my_f;
+        } else {
+          ++my_n;
+        }
       }
     }
+    const int in_n = wave_incl_scan(my_n), in_f = wave_incl_scan(my_f);
+    if (fill && e < e1) {
+      int32_t on = nbase + nn + in_n - my_n, of = fbase + nf + in_f - my_f;
+      for (int32_t sg = ch.x; sg < ch.y; ++sg) {
+        if (farmask & (1u << (sg - ch.x)))
+          far_ts[of++] = make_int2((int)(cl + t), (int)sg);
+        else
+          near_idx[on++] = sg - (int32_t)cl;
+      }
+    }
+    nn += __shfl(in_n, 63, 64);
+    nf += __shfl(in_f, 63, 64);
   }
-  if (!fill) {
+  if (!fill && lane == 0) {
     near_cnt[t] = nn;
     far_cnt[t] = nf;
   }
@@ -481,6 +520,11 @@ __global__ void k_offset_keys(const int2 *__restrict__ ts, int64_t n, const int3
   }
   key[i] = (uint32_t)id;
   idx[i] = (int32_t)i;
+}
+
+// *p = v (a small constant without a host copy)
+__global__ void k_set_i32(int32_t *p, int32_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 __global__ void k_group_flags(const uint32_t *__restrict__ key, int64_t n, int32_t *__restrict__ flag) {
@@ -992,7 +1036,6 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     copy_d2d(T.cchild.p + o, Uchild[l].p, C, s);
     copy_d2d(T.cparent.p + o, Upar[l].p, C, s);
   }
-  HIP_OK(hipStreamSynchronize(s));
   // convert level-local parent / child indices to global ones on the host
   // side of a small pass (counts are per level)
   {
@@ -1037,19 +1080,19 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
   std::vector<DBuf<int32_t>> fptr_l(L + 1);
   nptr[0].alloc(2);
   nidx[0].alloc(1);
-  {
-    int32_t h[2] = {0, 1}, z = 0;
-    HIP_OK(hipMemcpyAsync(nptr[0].p, h, 8, hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(nidx[0].p, &z, 4, hipMemcpyHostToDevice, s));
-    HIP_OK(hipStreamSynchronize(s));
-  }
+  // the root is near itself: nptr[0] = {0, 1}, nidx[0] = {0}
+  k_set_i32<<<1, 1, 0, s>>>(nptr[0].p, 0);
+  k_set_i32<<<1, 1, 0, s>>>(nptr[0].p + 1, 1);
+  k_set_i32<<<1, 1, 0, s>>>(nidx[0].p, 0);
+  LAUNCH_OK();
   nnear_l[0] = 1;
   for (int l = 1; l <= L; ++l) {
     int32_t C = T.ncell[l];
+    if (C == 0) BF_THROW(BEMFMM_EDEVICE, "tree build: empty level");
     DBuf<int32_t> ncnt, fcnt;
     ncnt.alloc(C + 1);
     fcnt.alloc(C + 1);
-    k_lists<<<cdiv(C, TB), TB, 0, s>>>(C, T.coff[l], T.coff[l - 1], T.cparent.p, T.cxyz.p, T.cchild.p, nptr[l - 1].p,
+    k_lists<<<C, 64, 0, s>>>(C, T.coff[l], T.coff[l - 1], T.cparent.p, T.cxyz.p, T.cchild.p, nptr[l - 1].p,
                                         nidx[l - 1].p, theta2, T.prm.mac, 0, ncnt.p, fcnt.p, nullptr, nullptr,
                                         nullptr, nullptr);
     LAUNCH_OK();
@@ -1062,7 +1105,7 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     exclusive_scan_i32(fcnt.p, fptr_l[l].p, C + 1, s, &nf);
     nidx[l].alloc(std::max<int32_t>(nn, 1));
     fts[l].alloc(std::max<int32_t>(nf, 1));
-    k_lists<<<cdiv(C, TB), TB, 0, s>>>(C, T.coff[l], T.coff[l - 1], T.cparent.p, T.cxyz.p, T.cchild.p, nptr[l - 1].p,
+    k_lists<<<C, 64, 0, s>>>(C, T.coff[l], T.coff[l - 1], T.cparent.p, T.cxyz.p, T.cchild.p, nptr[l - 1].p,
                                         nidx[l - 1].p, theta2, T.prm.mac, 1, nullptr, nullptr, nptr[l].p, nidx[l].p,
                                         fptr_l[l].p, fts[l].p);
     LAUNCH_OK();
@@ -1090,11 +1133,8 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     k_far_ptr<<<cdiv(T.ncell[l], TB), TB, 0, s>>>(fptr_l[l].p, T.ncell[l], T.coff[l], T.far_off[l], T.far_ptr.p);
     LAUNCH_OK();
   }
-  {
-    int32_t tot = (int32_t)T.nfar;
-    HIP_OK(hipMemcpyAsync(T.far_ptr.p + CT, &tot, 4, hipMemcpyHostToDevice, s));
-    HIP_OK(hipStreamSynchronize(s));
-  }
+  k_set_i32<<<1, 1, 0, s>>>(T.far_ptr.p + CT, (int32_t)T.nfar);
+  LAUNCH_OK();
 
   // M2L pairs sorted by translation offset (all levels together: the scaled
   // operator depends on the offset only), then one filtered list per
