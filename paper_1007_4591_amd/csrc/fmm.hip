@@ -523,22 +523,23 @@ template <> struct VecT<double> { using T = double2; static constexpr int W = 2;
 // leaf level the kernel also writes the evaluation coefficients
 // E[leaf][4][ps] of the potential and of its gradient (see L2P).
 template <class R>
-__global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int64_t C, int with_parent,
-                                                 const R *__restrict__ l2l, const int32_t *__restrict__ kptr,
-                                                 const R *__restrict__ m2l, R *__restrict__ Lx, int leaf, R inv_s,
-                                                 R *__restrict__ E) {
+__global__ void __launch_bounds__(256) k_downward(int p, int ps, int64_t c0, int64_t C, int with_parent,
+                                                  const R *__restrict__ l2l, const int32_t *__restrict__ kptr,
+                                                  const R *__restrict__ m2l, R *__restrict__ Lx, int leaf, R inv_s,
+                                                  R *__restrict__ E) {
   using VT = typename VecT<R>::T;
   constexpr int W = VecT<R>::W;
   constexpr int U = 8;
   extern __shared__ char smem_raw[];
+  const int nthr = blockDim.x;                // 64 or 256
   R *Ls = reinterpret_cast<R *>(smem_raw);     // [ps]
-  R *part = Ls + ps;                          // [64 * W] group partials
+  R *part = Ls + ps;                          // [nthr * W] group partials
   const int64_t c = c0 + blockIdx.x;
   if (blockIdx.x >= C) return;
   const int lane = threadIdx.x;
   const int np2 = p * p;
   const int lpr = ps / W;                     // lanes per row
-  const int groups = 64 / lpr;                // rows per step
+  const int groups = nthr / lpr;              // rows per step
   const int grp = lane / lpr, k4 = lane - grp * lpr;
   const bool act = grp < groups;
   R s[W], comp[W];
@@ -577,7 +578,7 @@ __global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int6
   for (int w = 0; w < W; ++w) part[lane * W + w] = s[w];
   __syncthreads();
   // group totals in group order -> Ls[k]
-  for (int k = lane; k < ps; k += 64) {
+  for (int k = lane; k < ps; k += nthr) {
     const int kk = k / W, w = k - kk * W;
     R acc = part[kk * W + w], cc = R(0);
     for (int h = 1; h < groups; ++h) {
@@ -591,17 +592,17 @@ __global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int6
   __syncthreads();
   if (with_parent) {
     const R *Lc = l2l + (size_t)blockIdx.x * ps;
-    for (int k = lane; k < ps; k += 64) Ls[k] += Lc[k];
+    for (int k = lane; k < ps; k += nthr) Ls[k] += Lc[k];
   }
   __syncthreads();
   R *out = Lx + (size_t)c * ps;
-  for (int k = lane; k < ps; k += 64) out[k] = Ls[k];
+  for (int k = lane; k < ps; k += nthr) out[k] = Ls[k];
   if (!leaf) return;
   // evaluation coefficients of the leaf (scaled to physical units):
   // phi(x) = sum_k E0[k] * Rpacked_k(rho), grad phi = sum_k E{x,y,z}[k] * Rpacked_k(rho)
   R *Ec = E + (size_t)blockIdx.x * 4 * ps;
   const R inv_s2 = inv_s * inv_s;
-  for (int k = lane; k < ps; k += 64) {
+  for (int k = lane; k < ps; k += nthr) {
     Ec[k] = R(0);
     Ec[ps + k] = R(0);
     Ec[2 * ps + k] = R(0);
@@ -619,7 +620,7 @@ __global__ void __launch_bounds__(64) k_downward(int p, int ps, int64_t c0, int6
     // L^{-m} = (-1)^m conj(L^m)
     return ((-m) & 1) ? Ls[idx_im(n, -m)] : -Ls[idx_im(n, -m)];
   };
-  for (int k = lane; k < np2; k += 64) {
+  for (int k = lane; k < np2; k += nthr) {
     int n = 0;
     while ((n + 1) * (n + 1) <= k) ++n;
     const int rem = k - n * n;
@@ -1255,9 +1256,12 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
           LAUNCH_OK();
         }
       }
-      const size_t shm2 = (size_t)(ps + 64 * VecT<R>::W) * sizeof(R);
-      k_downward<R><<<T.ncell[l], 64, shm2, s>>>(p, ps, T.coff[l], T.ncell[l], l > 2 ? 1 : 0, l2l, ML.kptr.p, m2l,
-                                                 Lx, leaf ? 1 : 0, R(1.0 / sL), E);
+      // levels with few cells (long interaction lists, too few waves to hide
+      // the load latency) take four waves per cell
+      const int nthr = T.ncell[l] < 4 * T.n_cu * 8 ? 256 : 64;
+      const size_t shm2 = (size_t)(ps + nthr * VecT<R>::W) * sizeof(R);
+      k_downward<R><<<T.ncell[l], nthr, shm2, s>>>(p, ps, T.coff[l], T.ncell[l], l > 2 ? 1 : 0, l2l, ML.kptr.p,
+                                                   m2l, Lx, leaf ? 1 : 0, R(1.0 / sL), E);
       LAUNCH_OK();
     }
     prof_end(T, ST_L2L, s);
