@@ -728,7 +728,11 @@ struct P2PArgs {
 template <class R, int SRC, int TGT, int OUT>
 __global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
   using R4 = typename V4<R>::T;
-  __shared__ R red[4][64];
+  // staged source records during the sweep, group partials after it (the
+  // two never live at once: 64 real4 = 4 x 64 reals)
+  __shared__ R4 src_s[64];
+  __shared__ R4 dip_s[(SRC == SRC_PANEL_DIP || SRC == SRC_PANEL_MONODIP) ? 64 : 1];
+  R(*red)[64] = reinterpret_cast<R(*)[64]>(src_s);
   // (leaf, first target, count, groups); chunks are in Morton order
   const int4 ch = a.chunks[xcd_block(blockIdx.x, gridDim.x)];
   const int leaf = ch.x, count = ch.z, G = ch.w;
@@ -819,23 +823,36 @@ __global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
           pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
         }
       }
-    } else if (active) {
-      if (self) {
-        for (int j = sb + g; j < se; j += G) {
-          const R4 s4 = spos[j];
-          const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
-          const R r2 = dx * dx + dy * dy + dz * dz;
-          const R ri = (j == ti) ? R(0) : rsq(r2);
-          pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
+    } else {
+      // several lane groups: the source leaf is staged in LDS, 64 records at
+      // a time, with one coalesced load; every lane group then reads its own
+      // sources there (a group's lanes read the same record: a broadcast)
+      constexpr bool DIPS = SRC == SRC_PANEL_DIP || SRC == SRC_PANEL_MONODIP;
+      for (int base = sb; base < se; base += 64) {
+        const int cnt = min(64, se - base);
+        __syncthreads();  // the previous records are no longer read
+        if (lane < cnt) {
+          src_s[lane] = spos[base + lane];
+          if (DIPS) dip_s[lane] = sdip[base + lane];
         }
-      } else {
+        __syncthreads();
+        if (!active) continue;
+        if (self) {
+          for (int jj = g; jj < cnt; jj += G) {
+            const R4 s4 = src_s[jj];
+            const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
+            const R r2 = dx * dx + dy * dy + dz * dz;
+            const R ri = (base + jj == ti) ? R(0) : rsq(r2);
+            pair_eval<R, SRC, OUT>(s4, DIPS ? dip_s[jj] : s4, dx, dy, dz, ri, lp, lx, ly, lz);
+          }
+        } else {
 #pragma unroll 4
-        for (int j = sb + g; j < se; j += G) {
-          const R4 s4 = spos[j];
-          const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
-          const R r2 = dx * dx + dy * dy + dz * dz;
-          const R ri = rsq(r2);
-          pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
+          for (int jj = g; jj < cnt; jj += G) {
+            const R4 s4 = src_s[jj];
+            const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
+            const R r2 = dx * dx + dy * dy + dz * dz;
+            pair_eval<R, SRC, OUT>(s4, DIPS ? dip_s[jj] : s4, dx, dy, dz, rsq(r2), lp, lx, ly, lz);
+          }
         }
       }
     }
@@ -851,6 +868,7 @@ __global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
   }
   // ---- combine the G lane groups in group order
   if (G > 1) {
+    __syncthreads();  // the last staged records are no longer read
     red[0][lane] = sp;
     red[1][lane] = sx;
     red[2][lane] = sy;
