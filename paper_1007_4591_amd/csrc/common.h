@@ -194,17 +194,17 @@ struct Tree {
   const Tables *tab = nullptr;
   const float *t_m2l32 = nullptr;   // [noff][PS/4 kk][PS/16 ct][64 lanes], MFMA B-operand order
   const double *t_m2l64 = nullptr;  // same layout
-  const float *t_m2m32 = nullptr;   // [8][ps in][ps out] (transposed)
-  const double *t_m2m64 = nullptr;
-  const float *t_l2l32 = nullptr;   // [8 octants][PS/4 kk][PS/16 ct][64 lanes], MFMA B-operand order
-  const double *t_l2l64 = nullptr;
+  // M2M and L2L: [8 octants][PS/4 kk][PS/16 ct][64 lanes], MFMA B-operand order
+  const float *t_m2m32 = nullptr, *t_l2l32 = nullptr;
+  const double *t_m2m64 = nullptr, *t_l2l64 = nullptr;
 
-  // L2L as batched MFMA products, per level l >= 3: rows are the level's
-  // cells grouped by octant (the operator depends on the octant only);
-  // src = parent cell (global index), dest = cell index within the level.
-  // Tiles of level l are [t0[l], t1[l]) (FP32) and [t0_64[l], t1_64[l]).
+  // L2L and M2M as batched MFMA products, per level l >= 3: rows are the
+  // level's cells grouped by octant (the operators depend on the octant
+  // only); src = parent cell (L2L input), self = the cell (M2M input), both
+  // global indices; dest = cell index within the level.  Tiles of level l
+  // are [t0[l], t1[l]) (FP32) and [t0_64[l], t1_64[l]).
   struct L2LList {
-    DBuf<int32_t> src, dest, group_off, group_end;
+    DBuf<int32_t> src, self, dest, group_off, group_end;
     DBuf<int32_t> tile_group, tile_row, tile_group64, tile_row64;
     std::vector<int64_t> t0, t1, t0_64, t1_64;
     int64_t max_cells = 0;

@@ -224,32 +224,20 @@ __global__ void __launch_bounds__(64) k_p2m(int p, int ps, int64_t C, const int4
 
 // -------------------------------------------------------------------- M2M
 
-// One wave per parent cell at one level: M(parent) = sum over children of
-// S_oct M(child); S stored transposed [oct][in][out] so lanes read rows.
+// M2M, second half: the multipole expansion of every cell of level l - 1 is
+// the sum of its children's translated expansions (rows of the batched M2M
+// product of level l, one per child), added in child order.
 template <class R>
-__global__ void __launch_bounds__(64) k_m2m(int np2, int ps, int64_t c0, int64_t C, const int2 *__restrict__ child,
-                                            const uint32_t *__restrict__ ckey, const R *__restrict__ St,
-                                            R *__restrict__ M) {
-  const int64_t c = c0 + blockIdx.x;
-  if (blockIdx.x >= C) return;
-  const int lane = threadIdx.x;
-  const int2 ch = child[c];
-  R acc0 = R(0), acc1 = R(0), acc2 = R(0);
-  for (int cc = ch.x; cc < ch.y; ++cc) {
-    const int oct = ckey[cc] & 7;
-    const R *S = St + (size_t)oct * ps * ps;
-    const R *Mc = M + (size_t)cc * ps;
-    for (int j = 0; j < np2; ++j) {
-      const R mj = Mc[j];
-      acc0 += S[(size_t)j * ps + lane] * mj;
-      if (lane + 64 < ps) acc1 += S[(size_t)j * ps + lane + 64] * mj;
-      if (lane + 128 < ps) acc2 += S[(size_t)j * ps + lane + 128] * mj;
-    }
-  }
-  R *out = M + (size_t)c * ps;
-  out[lane] = acc0;
-  if (lane + 64 < ps) out[lane + 64] = acc1;
-  if (lane + 128 < ps) out[lane + 128] = acc2;
+__global__ void k_m2m_sum(int ps, int64_t cp0, int64_t CP, int64_t cl0, const int2 *__restrict__ child,
+                          const R *__restrict__ rows, R *__restrict__ M) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= CP * ps) return;
+  const int64_t P = i / ps;
+  const int k = (int)(i - P * ps);
+  const int2 ch = child[cp0 + P];  // global child range
+  R acc = R(0);
+  for (int c = ch.x; c < ch.y; ++c) acc += rows[(size_t)(c - cl0) * ps + k];
+  M[(size_t)(cp0 + P) * ps + k] = acc;
 }
 
 // -------------------------------------------------------------------- M2L
@@ -1095,6 +1083,46 @@ static void launch_p2m(Tree &T, PrecBufs &B, int src, hipStream_t s) {
   LAUNCH_OK();
 }
 
+// Batched per-level product on the MFMA kernel: for every cell c of level
+// l (l >= 3), out[c - coff[l]] = S_oct(c) in[src[c]], with the per-octant
+// operator table S (M2M: src = the cell, L2L: src = its parent).
+template <class R, int USE>
+static void level_product(Tree &T, int l, const int32_t *src, const void *table, const R *in, R *out,
+                          hipStream_t s) {
+  const bool f64 = std::is_same<R, double>::value;
+  const Tree::L2LList &LW = T.l2lw;
+  const int64_t t0 = f64 ? LW.t0_64[l] : LW.t0[l], t1 = f64 ? LW.t1_64[l] : LW.t1[l];
+  if (t1 <= t0) return;
+  const dim3 grid((unsigned)(t1 - t0));
+#define LEVEL_CASE(nt)                                                                                          \
+  case nt:                                                                                                      \
+    if (f64)                                                                                                    \
+      k_m2l<double, nt, M2L_RT64, false, USE><<<grid, 256, 0, s>>>(                                             \
+          LW.tile_group64.p + t0, LW.tile_row64.p + t0, LW.group_off.p, LW.group_end.p, src, LW.dest.p,         \
+          reinterpret_cast<const double *>(table), reinterpret_cast<const double *>(in),                        \
+          reinterpret_cast<double *>(out));                                                                     \
+    else                                                                                                        \
+      k_m2l<float, nt, M2L_RT32, true, USE><<<grid, 256, 0, s>>>(                                               \
+          LW.tile_group.p + t0, LW.tile_row.p + t0, LW.group_off.p, LW.group_end.p, src, LW.dest.p,             \
+          reinterpret_cast<const float *>(table), reinterpret_cast<const float *>(in),                          \
+          reinterpret_cast<float *>(out));                                                                      \
+    break;
+  switch (T.ps / 16) {
+    LEVEL_CASE(1)
+    LEVEL_CASE(2)
+    LEVEL_CASE(3)
+    LEVEL_CASE(4)
+    LEVEL_CASE(5)
+    LEVEL_CASE(6)
+    LEVEL_CASE(7)
+    LEVEL_CASE(8)
+    default:
+      BF_THROW(BEMFMM_EINVAL, "unsupported expansion order");
+  }
+#undef LEVEL_CASE
+  LAUNCH_OK();
+}
+
 template <class R>
 static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   using R4 = typename V4<R>::T;
@@ -1192,11 +1220,15 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     prof_begin(T, ST_P2M, s);
     launch_p2m<R>(T, B, rq.src, s);
     prof_end(T, ST_P2M, s);
-    // M2M, levels L-1 .. 2
+    // M2M, parents of levels L-1 .. 2: a batched MFMA product per child level
+    // (one row per child), then each parent adds its children's rows
     prof_begin(T, ST_M2M, s);
-    const R *Sm = f64 ? reinterpret_cast<const R *>(T.t_m2m64) : reinterpret_cast<const R *>(T.t_m2m32);
-    for (int l = L - 1; l >= 2; --l) {
-      k_m2m<R><<<T.ncell[l], 64, 0, s>>>(p * p, ps, T.coff[l], T.ncell[l], T.cchild.p, T.ckey.p, Sm, M);
+    const void *Sm = f64 ? (const void *)T.t_m2m64 : (const void *)T.t_m2m32;
+    R *rows = reinterpret_cast<R *>(B.l2l_out.p);
+    for (int l = L; l >= 3; --l) {
+      level_product<R, 2>(T, l, T.l2lw.self.p, Sm, M, rows, s);
+      const int64_t CP = T.ncell[l - 1];
+      k_m2m_sum<R><<<cdiv(CP * ps, TB), TB, 0, s>>>(ps, T.coff[l - 1], CP, T.coff[l], T.cchild.p, rows, M);
       LAUNCH_OK();
     }
     prof_end(T, ST_M2M, s);
@@ -1245,34 +1277,7 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
       const bool leaf = (l == L);
       if (l > 2) {
         // L2L of every cell of level l from its parent's final expansion
-        const int64_t t0 = f64 ? LW.t0_64[l] : LW.t0[l], t1 = f64 ? LW.t1_64[l] : LW.t1[l];
-        if (t1 > t0) {
-#define L2L_CASE(nt)                                                                                           \
-  case nt:                                                                                                     \
-    if (f64)                                                                                                   \
-      k_m2l<double, nt, M2L_RT64, false, 1><<<dim3((unsigned)(t1 - t0)), 256, 0, s>>>(                           \
-          LW.tile_group64.p + t0, LW.tile_row64.p + t0, LW.group_off.p, LW.group_end.p, LW.src.p, LW.dest.p,   \
-          T.t_l2l64, reinterpret_cast<const double *>(Lx), reinterpret_cast<double *>(l2l));                   \
-    else                                                                                                       \
-      k_m2l<float, nt, M2L_RT32, true, 1><<<dim3((unsigned)(t1 - t0)), 256, 0, s>>>(                              \
-          LW.tile_group.p + t0, LW.tile_row.p + t0, LW.group_off.p, LW.group_end.p, LW.src.p, LW.dest.p,       \
-          T.t_l2l32, reinterpret_cast<const float *>(Lx), reinterpret_cast<float *>(l2l));                     \
-    break;
-          switch (NT) {
-            L2L_CASE(1)
-            L2L_CASE(2)
-            L2L_CASE(3)
-            L2L_CASE(4)
-            L2L_CASE(5)
-            L2L_CASE(6)
-            L2L_CASE(7)
-            L2L_CASE(8)
-            default:
-              BF_THROW(BEMFMM_EINVAL, "unsupported expansion order");
-          }
-#undef L2L_CASE
-          LAUNCH_OK();
-        }
+        level_product<R, 1>(T, l, LW.src.p, f64 ? (const void *)T.t_l2l64 : (const void *)T.t_l2l32, Lx, l2l, s);
       }
       // levels with few cells (long interaction lists, too few waves to hide
       // the load latency) take four waves per cell

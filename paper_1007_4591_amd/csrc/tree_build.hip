@@ -710,8 +710,8 @@ struct DevTables {
 };
 }  // namespace
 
-// Work lists of the batched L2L products: per level l >= 3, the level's
-// cells grouped by octant, cut into MFMA tiles.  Built on the host from the
+// Work lists of the batched L2L and M2M products: per level l >= 3, the
+// level's cells grouped by octant, cut into MFMA tiles.  Built on the host from the
 // cell keys and parents (a few tens of thousands of cells).
 static void build_l2l_lists(Tree &T, hipStream_t s) {
   Tree::L2LList &W = T.l2lw;
@@ -727,7 +727,7 @@ static void build_l2l_lists(Tree &T, hipStream_t s) {
   HIP_OK(hipMemcpyAsync(key.data(), T.ckey.p, T.ncell_tot * 4, hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(par.data(), T.cparent.p, T.ncell_tot * 4, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  std::vector<int32_t> src, dest, goff, gend, tg, tr, tg64, tr64;
+  std::vector<int32_t> src, self, dest, goff, gend, tg, tr, tg64, tr64;
   for (int l = 3; l <= L; ++l) {
     W.t0[l] = (int64_t)tg.size();
     W.t0_64[l] = (int64_t)tg64.size();
@@ -737,6 +737,7 @@ static void build_l2l_lists(Tree &T, hipStream_t s) {
       for (int64_t c = c0; c < c1; ++c)
         if ((key[c] & 7u) == o) {
           src.push_back(par[c]);
+          self.push_back((int32_t)c);
           dest.push_back((int32_t)(c - c0));
         }
       const int32_t e = (int32_t)src.size();
@@ -762,6 +763,7 @@ static void build_l2l_lists(Tree &T, hipStream_t s) {
     if (!h.empty()) HIP_OK(hipMemcpyAsync(d.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, s));
   };
   up(W.src, src);
+  up(W.self, self);
   up(W.dest, dest);
   up(W.group_off, goff);
   up(W.group_end, gend);
@@ -808,19 +810,17 @@ void upload_tables(Tree &T, hipStream_t s) {
     D->m2l64.alloc(sw64.size());
     HIP_OK(hipMemcpyAsync(D->m2l32.p, sw32.data(), sw32.size() * 4, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(D->m2l64.p, sw64.data(), sw64.size() * 8, hipMemcpyHostToDevice, s));
-    // M2M stored transposed, [oct][in][out], so that lanes of a wave (one
-    // output coefficient each) read consecutive words; L2L in the MFMA
-    // B-operand order of the M2L tables, one per octant
-    std::vector<double> a((size_t)8 * ps * ps), b((size_t)8 * KK * NT * 64);
-    for (int o = 0; o < 8; ++o)
-      for (int r = 0; r < ps; ++r)
-        for (int c = 0; c < ps; ++c) a[((size_t)o * ps + c) * ps + r] = tb.m2m[((size_t)o * ps + r) * ps + c];
+    // M2M and L2L in the MFMA B-operand order of the M2L tables, one per
+    // octant (the batched per-level products reuse the M2L kernel)
+    std::vector<double> a((size_t)8 * KK * NT * 64), b(a.size());
     for (int o = 0; o < 8; ++o)
       for (int kk = 0; kk < KK; ++kk)
         for (int ct = 0; ct < NT; ++ct)
           for (int l = 0; l < 64; ++l) {
             const int out = ct * 16 + (l % 16), in = (l / 16) * KK + kk;
-            b[(((size_t)o * KK + kk) * NT + ct) * 64 + l] = tb.l2l[((size_t)o * ps + out) * ps + in];
+            const size_t at = (((size_t)o * KK + kk) * NT + ct) * 64 + l;
+            a[at] = tb.m2m[((size_t)o * ps + out) * ps + in];
+            b[at] = tb.l2l[((size_t)o * ps + out) * ps + in];
           }
     std::vector<float> a32(a.size()), b32(b.size());
     for (size_t i = 0; i < a.size(); ++i) a32[i] = (float)a[i];
