@@ -178,6 +178,23 @@ def main():
                 "achieved": m2l_flops / (m2l_ms / 1e3) / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
                 "avg_ms": m2l_ms, "launches": live["m2l"][1], "traffic": pmc_traffic("k_m2l_pers<7, 4>")}
     roof_m2l["frac"] = roof_m2l["achieved"] / roof_m2l["peak"]
+    # the same kernels alone on the chip (near field not concurrent): a
+    # second tree built with the concurrent near field switched off
+    # (the library reads the switch at a tree's first product)
+    os.environ["BEMFMM_CONCURRENT_P2P"] = "0"
+    tree_alone = B.build_tree(verts, tris, cpos, params)
+    for _ in range(3):
+        B.fmm_matvec(tree_alone, B.OP_A, B.FP32, xv, yv)
+    del os.environ["BEMFMM_CONCURRENT_P2P"]
+    B.profile(tree_alone, True, True)
+    for _ in range(nprof):
+        B.fmm_matvec(tree_alone, B.OP_A, B.FP32, xv, yv)
+    for r, stage, flops in ((roof_p2p, "p2p", p2p_flops), (roof_m2l, "m2l", m2l_flops)):
+        ms, n = B.profile_get(tree_alone, f"{stage}/{B.OP_A}/{B.FP32}")
+        r["standalone_avg_ms"] = ms / max(n, 1)
+        r["standalone_frac"] = flops / (r["standalone_avg_ms"] / 1e3) / r["peak"] / 1e12
+    B.profile(tree_alone, False, True)
+    B.tree_destroy(tree_alone)
     roofline = roof_p2p if p2p_ms >= m2l_ms else roof_m2l
     print(f"[bench] stages(ms, count)={stages}", file=sys.stderr, flush=True)
 
