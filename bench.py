@@ -102,6 +102,7 @@ def main():
         t = B.build_tree(verts, tris, cpos, params)
         if record:
             B.profile(t, True, True)
+            B.profile_select(t, B.OP_A, B.FP32)  # other products record nothing
         x, info = B.solve_bem(t, q, tol=TOL, maxit=300, restart=30, precision=B.FP32_REFINED)
         dG = B.solvation_energy(t, q, x, precision=B.FP64)
         bib = B.bibee_energy(t, q, kind=B.BIBEE_CFA, precision=B.FP32)

@@ -234,6 +234,11 @@ int bemfmm_debug_fields(bemfmm_tree *tree, int precision, double *near_host, dou
  * one precision (BEMFMM_FP64 = 0, BEMFMM_FP32 = 1).  ms_host and
  * count_host receive the total time and the number of stage instances. */
 int bemfmm_profile(bemfmm_tree *tree, int enable, int reset);
+/* Restrict recording to products of one operator (BEMFMM_OP_*, or -1 for
+ * any) at one precision (BEMFMM_FP64, BEMFMM_FP32, or -1 for any; a refined
+ * solve runs FP32 and FP64 products).  Other products then record no events
+ * and wait for nothing. */
+int bemfmm_profile_select(bemfmm_tree *tree, int op, int precision);
 int bemfmm_profile_get(bemfmm_tree *tree, const char *stage, double *ms_host, int64_t *count_host);
 
 #ifdef __cplusplus

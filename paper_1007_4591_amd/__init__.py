@@ -113,10 +113,11 @@ def _load():
     lib.bemfmm_profile.argtypes = [P, I, I]
     lib.bemfmm_profile_get.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)]
     lib.bemfmm_release_cache.argtypes = []
+    lib.bemfmm_profile_select.argtypes = [P, I, I]
     for name in ("bemfmm_build_tree", "bemfmm_set_charges", "bemfmm_tree_destroy", "bemfmm_tree_get_info",
                  "bemfmm_fmm_matvec", "bemfmm_solve_bem", "bemfmm_bibee_energy", "bemfmm_solvation_energy",
                  "bemfmm_adjoint_grad", "bemfmm_tree_export", "bemfmm_debug_expansions", "bemfmm_debug_fields",
-                 "bemfmm_profile", "bemfmm_profile_get", "bemfmm_release_cache"):
+                 "bemfmm_profile", "bemfmm_profile_get", "bemfmm_release_cache", "bemfmm_profile_select"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -330,6 +331,11 @@ def profile(tree: Tree, enable: bool, reset: bool = True):
     _check(_load().bemfmm_profile(tree.handle, 1 if enable else 0, 1 if reset else 0))
 
 
+def profile_select(tree: Tree, op: int = -1, precision: int = -1):
+    """Record stage times only for products of `op` at `precision` (-1: any)."""
+    _check(_load().bemfmm_profile_select(tree.handle, int(op), int(precision)))
+
+
 def release_cache():
     """Return the device memory the library keeps cached for reuse."""
     _check(_load().bemfmm_release_cache())
@@ -347,5 +353,5 @@ __all__ = [
     "MAC_THETA", "MAC_ADJACENT", "Params", "SolveInfo", "Tree", "BemfmmError", "NotConverged", "build_tree",
     "set_charges", "tree_destroy", "fmm_matvec", "solve_bem", "bibee_energy", "solvation_energy", "adjoint_grad",
     "tree_export", "debug_expansions", "debug_fields", "profile", "profile_get", "library_path",
-    "release_cache",
+    "release_cache", "profile_select",
 ]

@@ -251,6 +251,17 @@ int bemfmm_profile(bemfmm_tree *tree, int enable, int reset) {
   });
 }
 
+int bemfmm_profile_select(bemfmm_tree *tree, int op, int precision) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    need(op >= -1 && op < 6, "op must be -1 or a BEMFMM_OP_* value");
+    need(precision == -1 || precision == BEMFMM_FP64 || precision == BEMFMM_FP32,
+         "precision must be -1, BEMFMM_FP64 or BEMFMM_FP32");
+    T->prof_op = op;
+    T->prof_sel_prec = precision == -1 ? -1 : (precision == BEMFMM_FP64 ? 0 : 1);
+  });
+}
+
 int bemfmm_profile_get(bemfmm_tree *tree, const char *stage, double *ms_host, int64_t *count_host) {
   return guard([&] {
     Tree *T = check_tree(tree);

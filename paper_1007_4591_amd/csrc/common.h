@@ -234,6 +234,8 @@ struct Tree {
   int n_cu = 256;                // compute units of the device
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool prof = false;
+  int prof_op = -1, prof_sel_prec = -1;  // record only this operator / precision (-1: any)
+  bool prof_now = false;                  // the product being run is recorded
   // stage times per [product kind: the six operators, then any other][FP64, FP32][stage]
   double prof_ms[7][2][7] = {};
   int64_t prof_cnt[7][2][7] = {};

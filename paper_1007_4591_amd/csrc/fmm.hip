@@ -1006,18 +1006,18 @@ void set_rec_constants() {
 // read after the product has finished, so profiling does not serialise the
 // two streams.
 void prof_begin(Tree &T, int stage, hipStream_t s) {
-  if (!T.prof) return;
+  if (!T.prof_now) return;
   HIP_OK(hipEventRecord(T.ev[2 * stage], s));
 }
 
 void prof_end(Tree &T, int stage, hipStream_t s) {
-  if (!T.prof) return;
+  if (!T.prof_now) return;
   HIP_OK(hipEventRecord(T.ev[2 * stage + 1], s));
   T.prof_pending[stage] = true;
 }
 
 static void prof_collect(Tree &T) {
-  if (!T.prof) return;
+  if (!T.prof_now) return;
   for (int st = 0; st < 7; ++st) {
     if (!T.prof_pending[st]) continue;
     HIP_OK(hipEventSynchronize(T.ev[2 * st + 1]));
@@ -1328,6 +1328,7 @@ void fmm_apply(Tree &T, int precision, const FmmRequest &rq, hipStream_t s) {
   }
   T.prof_kind = (rq.op >= 0 && rq.op < 6) ? rq.op : 6;
   T.prof_prec = prec == BEMFMM_FP64 ? 0 : 1;
+  T.prof_now = T.prof && (T.prof_op < 0 || T.prof_op == rq.op) && (T.prof_sel_prec < 0 || T.prof_sel_prec == T.prof_prec);
   if (prec == BEMFMM_FP64)
     run_fmm<double>(T, B, rq, s);
   else
