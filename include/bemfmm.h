@@ -31,6 +31,19 @@
  *   The tree stays valid except after BEMFMM_EDEVICE.
  * - Expansion order p means degrees 0..p-1 (p^2 real coefficients per
  *   expansion; p = 10 gives the 55 complex coefficients of Section 3.2).
+ * - Each tree also owns one non-blocking stream (default priority) on which
+ *   the near field of a product runs beside the multipole passes.  Events
+ *   order it after the caller's earlier work on `stream` and before the
+ *   product's last kernel on `stream`, so the caller sees plain stream order.
+ * - Every product is deterministic: the same tree, inputs and precision
+ *   give bitwise the same result (no floating-point atomics).
+ * - Environment switches, read when a tree runs its first product (or, for
+ *   the cache, on first use): BEMFMM_CONCURRENT_P2P=0 runs the near field
+ *   on `stream` after the multipole passes; BEMFMM_M2L_PERSISTENT=0 uses one
+ *   workgroup per FP32 M2L tile instead of persistent workgroups;
+ *   BEMFMM_CACHE_LIMIT_MB caps the device memory kept for reuse per device
+ *   (default 32768, see bemfmm_release_cache).  Results do not depend on the
+ *   first two.
  */
 #ifndef BEMFMM_H
 #define BEMFMM_H
