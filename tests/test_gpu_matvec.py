@@ -193,3 +193,24 @@ def test_rebuild_after_destroy_reuses_memory_bitwise():
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
+
+
+def test_switches_do_not_change_results(monkeypatch):
+    """The near field run concurrently or after the multipole passes, and the
+    FP32 M2L with persistent or one-tile workgroups, give bitwise the same
+    products (the switches change scheduling, not arithmetic)."""
+    B = lib()
+    p = synth.blobby(5)
+    x, y, qv = _inputs(p)
+    outs = {}
+    for conc, pers in (("1", "1"), ("0", "1"), ("1", "0")):
+        monkeypatch.setenv("BEMFMM_CONCURRENT_P2P", conc)
+        monkeypatch.setenv("BEMFMM_M2L_PERSISTENT", pers)
+        t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params())
+        outs[(conc, pers)] = {prec: _run_all(B, t, x, y, qv, prec) for prec in (0, 1)}
+        B.tree_destroy(t)
+    ref = outs[("1", "1")]
+    for key, o in outs.items():
+        for prec in (0, 1):
+            for op in range(6):
+                assert np.array_equal(o[prec][op], ref[prec][op]), (key, prec, op)
