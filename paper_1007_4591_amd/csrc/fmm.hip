@@ -1,12 +1,15 @@
-// Fast-multipole evaluation (Section 2.3) on gfx950: one pass of
-//   pack sources -> P2M (leaves) -> M2M (levels L-1..2) -> M2L (all levels,
-//   grouped by translation offset, dense contractions on MFMA) ->
-//   downward pass (ordered reduction of M2L results + L2L, levels 2..L) ->
-//   P2P near field fused with L2P and the operator's final combination.
+// Fast-multipole evaluation (Section 2.3) on gfx950.  One product runs
+//   pack sources -> P2M (leaves) -> M2M (levels L..3 to their parents,
+//   batched MFMA products per level and octant) -> M2L (all levels, grouped
+//   by translation offset, dense contractions on MFMA) -> downward pass
+//   (batched MFMA L2L + ordered sum of the M2L results, levels 2..L, and the
+//   leaves' evaluation coefficients) -> L2P fused with the operator's final
+//   combination,
+// while the P2P near field runs on a second stream and is joined before L2P.
 //
 // Every stage is templated on the working precision (float or double); the
-// FP32 path uses v_mfma_f32_16x16x4f32 for M2L and v_rsq_f32 in P2P, the
-// FP64 path v_mfma_f64_16x16x4f64 and a refined FP64 reciprocal square root.
+// FP32 path uses v_mfma_f32_16x16x4f32 and v_rsq_f32, the FP64 path
+// v_mfma_f64_16x16x4f64 and a refined FP64 reciprocal square root.
 // Accumulation orders are fixed (no floating-point atomics), so results are
 // reproducible run to run.
 #include <algorithm>
@@ -264,13 +267,16 @@ __device__ __forceinline__ int xcd_block(int bid, int n) {
 // source row: at k-step kk, lane group g = lane/16 supplies input g*KK + kk
 // (the B table is stored in that order).  Rows past the end of the group
 // repeat its last row (MFMA rows are independent; they are not stored).
-// USE only names the instance (0: M2L, 1: the batched L2L), so that
-// profiles tell the two apart.
+// The same kernel runs the batched per-level M2M and L2L products (one
+// octant operator per group); USE only names the instance (0: M2L, 1: L2L,
+// 2: M2M) so that profiles tell them apart.
 // Registers are budgeted for two waves per SIMD so that one wave's gather
 // overlaps the other's MFMA work.  With BLDS the four waves of a tile share
 // the operator through LDS instead of each reading it from L2.
-// Each result row goes to its place in pair order (level, target, source),
-// so that the downward pass reads a cell's rows as one contiguous run.  Output layouts (checked on the device): FP32 16x16x4 puts
+// Each result row goes to dest[row]: for M2L its place in pair order
+// (level, target, source), so that the downward pass reads a cell's rows as
+// one contiguous run; for M2M and L2L the cell's index within its level.
+// Output layouts (checked on the device): FP32 16x16x4 puts
 // D[4*(lane/16) + q][lane%16] in register q; FP64 16x16x4 puts
 // D[lane/16 + 4*q][lane%16] in register q.
 template <class R, int NT, int RT, bool BLDS, int USE>
