@@ -38,16 +38,26 @@ P2P_FLOPS_PER_PAIR = 18      # K' monopole pair: 3 sub, 5 for r^2, 1 rsq, 3 mul,
 M2L_FLOPS_PER_PAIR = 2 * 100 * 100   # dense p^2 x p^2 contraction at p = 10
 
 
+def kernel_source_hash(path):
+    """SHA-256 of a source file's code: comments and whitespace removed, so
+    that only a change of the code itself invalidates measured figures."""
+    import hashlib
+    import re
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    text = re.sub(r"\s+", "", text)
+    return hashlib.sha256(text.encode()).hexdigest()
+
+
 def pmc_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed hardware-counter
     summary, or None when the kernel source changed since it was taken."""
-    import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", "pmc_traffic_blobby-L8.md")
-    src = os.path.join(here, "paper_1007_4591_amd", "csrc", "fmm.hip")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = kernel_source_hash(os.path.join(here, "paper_1007_4591_amd", "csrc", "fmm.hip"))
     for line in open(path):
         if line.startswith("| `" + kernel + "`"):
             cells = [c.strip() for c in line.strip().strip("|").split("|")]
