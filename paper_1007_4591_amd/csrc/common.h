@@ -28,6 +28,9 @@ namespace bemfmm {
 constexpr int KEY_BITS = 10;  // bits per axis of the Morton keys (30-bit keys)
 constexpr int LMAX = KEY_BITS;
 constexpr int PMAX = 12;
+// expansion order with kernels specialised at compile time (the order the
+// method is run at, Section 4); other orders take the generic kernels
+constexpr int P_FIXED = 10;
 // M2L work tiles: 4 waves x RT row tiles of 16 pairs
 constexpr int M2L_RT32 = 4, M2L_RT64 = 2;
 constexpr int M2L_ROWS32 = 4 * M2L_RT32 * 16, M2L_ROWS64 = 4 * M2L_RT64 * 16;

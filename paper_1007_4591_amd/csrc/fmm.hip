@@ -104,6 +104,44 @@ __device__ inline void regular_harmonics(int p, R x, R y, R z, F &&f) {
   }
 }
 
+// The same recurrences for an order P fixed at compile time: the loops
+// unroll completely, the recurrence coefficients fold to constants (computed
+// in FP64 and rounded to R, as the host tables are), and f receives constant
+// (n, m), so callers can keep one register per coefficient.
+template <int P, class R, class F>
+__device__ __forceinline__ void regular_harmonics_fixed(R x, R y, R z, F &&f) {
+  const R r2 = x * x + y * y + z * z;
+  R dr = R(1), di = R(0);
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    if (m > 0) {
+      const R c = -R(1.0 / (2.0 * m));
+      const R nr = c * (x * dr - y * di);
+      const R ni = c * (x * di + y * dr);
+      dr = nr;
+      di = ni;
+    }
+    f(m, m, dr, di);
+    if (m + 1 < P) {
+      R pr = dr, pi = di;
+      R qr = z * dr, qi = z * di;
+      f(m + 1, m, qr, qi);
+#pragma unroll
+      for (int n = m + 2; n < P; ++n) {
+        const double den = double(n * n - m * m);
+        const R a = R((2.0 * n - 1.0) / den) * z, b = R(1.0 / den) * r2;
+        const R nr = a * qr - b * pr;
+        const R ni = a * qi - b * pi;
+        f(n, m, nr, ni);
+        pr = qr;
+        pi = qi;
+        qr = nr;
+        qi = ni;
+      }
+    }
+  }
+}
+
 __device__ inline void xyz_of(int32_t v, int &x, int &y, int &z) {
   x = v & 1023;
   y = (v >> 10) & 1023;
@@ -222,6 +260,71 @@ __global__ void __launch_bounds__(64) k_p2m(int p, int ps, int64_t C, const int4
     R acc = R(0);
     for (int l = 0; l < 64; ++l) acc += row[l * stride + k];
     out[k] = acc;
+  }
+}
+
+// P2M for an order P fixed at compile time.  Same arithmetic and order as
+// k_p2m (each lane sums its own sources, then the lanes are added in lane
+// order), but a lane's partial expansion lives in registers while it sweeps
+// its sources; LDS is used once, to add the 64 partial rows column by column.
+template <int P, class R, bool MONO, bool DIP>
+__global__ void __launch_bounds__(64) k_p2m_fixed(int ps, int64_t C, const int4 *__restrict__ range, int charges,
+                                                  const typename V4<R>::T *__restrict__ src,
+                                                  const typename V4<R>::T *__restrict__ dip, R inv_s,
+                                                  R *__restrict__ M) {
+  constexpr int NC = P * P;
+  __shared__ R part[64][NC + 1];
+  const int lane = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  if (c >= C) return;
+  R acc[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) acc[k] = R(0);
+  const int4 rg = range[c];
+  const int b = charges ? rg.z : rg.x, e = charges ? rg.w : rg.y;
+  for (int j = b + lane; j < e; j += 64) {
+    const typename V4<R>::T sp = src[j];
+    const R x = sp.x * inv_s, y = sp.y * inv_s, z = sp.z * inv_s;
+    const R w = sp.w;
+    R mx = R(0), myy = R(0), mz = R(0);
+    if (DIP) {
+      const typename V4<R>::T mo = dip[j];
+      mx = mo.x * inv_s;
+      myy = mo.y * inv_s;
+      mz = mo.z * inv_s;
+    }
+    regular_harmonics_fixed<P, R>(x, y, z, [&](int n, int m, R re, R im) {
+      if (MONO) {
+        acc[idx_re(n, m)] += w * re;
+        if (m > 0) acc[idx_im(n, m)] -= w * im;
+      }
+      if (DIP && n <= P - 2) {
+        const int no = n + 1;
+        acc[idx_re(no, m)] += mz * re;
+        if (m > 0) acc[idx_im(no, m)] -= mz * im;
+        if (m >= 1) {
+          const R hr = R(0.5) * (mx * re + myy * im);
+          if (m == 1) {
+            acc[idx_re(no, 0)] += hr + hr;
+          } else {
+            acc[idx_re(no, m - 1)] += hr;
+            acc[idx_im(no, m - 1)] += R(0.5) * (myy * re - mx * im);
+          }
+        }
+        acc[idx_re(no, m + 1)] -= R(0.5) * (mx * re - myy * im);
+        acc[idx_im(no, m + 1)] += R(0.5) * (mx * im + myy * re);
+      }
+    });
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) part[lane][k] = acc[k];
+  __syncthreads();
+  R *out = M + c * ps;
+  for (int k = lane; k < ps; k += 64) {
+    R t = R(0);
+    if (k < NC)
+      for (int l = 0; l < 64; ++l) t += part[l][k];
+    out[k] = t;
   }
 }
 
@@ -901,7 +1004,9 @@ __global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
 // Far field (L2P from the leaf's evaluation coefficients, read through the
 // scalar cache) plus the near field, combined into the operator's output in
 // the caller's order: y = alpha x + beta (area) field.
-template <class R, int TGT, int OUT>
+// P > 0: the order fixed at compile time (P == a.p), so the harmonics unroll
+// and the coefficient loads are at constant offsets; P = 0: any order.
+template <class R, int TGT, int OUT, int P>
 __global__ void __launch_bounds__(64) k_l2p_combine(P2PArgs a) {
   using R4 = typename V4<R>::T;
   const int4 ch = a.chunks[blockIdx.x];
@@ -915,8 +1020,8 @@ __global__ void __launch_bounds__(64) k_l2p_combine(P2PArgs a) {
   R fp = R(0), fgx = R(0), fgy = R(0), fgz = R(0);
   {
     const R x = tp.x * inv_s, y = tp.y * inv_s, z = tp.z * inv_s;
-    const int p = a.p;
-    regular_harmonics<R>(p, x, y, z, [&](int n, int m, R re, R im) {
+    const int p = P > 0 ? P : a.p;
+    auto term = [&](int n, int m, R re, R im) {
       const int kr = idx_re(n, m);
       if (OUT != OUT_NGRAD) {
         fp += E[kr] * re;
@@ -933,7 +1038,11 @@ __global__ void __launch_bounds__(64) k_l2p_combine(P2PArgs a) {
           fgz += E[3 * a.ps + ki] * im;
         }
       }
-    });
+    };
+    if constexpr (P > 0)
+      regular_harmonics_fixed<P, R>(x, y, z, term);
+    else
+      regular_harmonics<R>(p, x, y, z, term);
   }
   const int64_t u = a.tperm[ti];
   double res[4], near_v, far_v;
@@ -1072,6 +1181,24 @@ static void launch_p2m(Tree &T, PrecBufs &B, int src, hipStream_t s) {
   R *M = reinterpret_cast<R *>(B.M.p) + (size_t)T.coff[L] * ps;
   const int4 *rg = T.crange.p + T.coff[L];
   const R inv = R(1.0 / sL);
+  if (T.p == P_FIXED) {
+    switch (src) {
+      case SRC_PANEL_MONO:
+        k_p2m_fixed<P_FIXED, R, true, false><<<CL, 64, 0, s>>>(ps, CL, rg, 0, spos, sdip, inv, M);
+        break;
+      case SRC_CHARGE_MONO:
+        k_p2m_fixed<P_FIXED, R, true, false><<<CL, 64, 0, s>>>(ps, CL, rg, 1, spos, sdip, inv, M);
+        break;
+      case SRC_PANEL_DIP:
+        k_p2m_fixed<P_FIXED, R, false, true><<<CL, 64, 0, s>>>(ps, CL, rg, 0, spos, sdip, inv, M);
+        break;
+      default:
+        k_p2m_fixed<P_FIXED, R, true, true><<<CL, 64, 0, s>>>(ps, CL, rg, 0, spos, sdip, inv, M);
+        break;
+    }
+    LAUNCH_OK();
+    return;
+  }
   switch (src) {
     case SRC_PANEL_MONO:
       k_p2m<R, true, false><<<CL, 64, shm, s>>>(T.p, ps, CL, rg, 0, spos, sdip, inv, M);
@@ -1302,13 +1429,21 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   if (nchunks > 0) {
     HIP_OK(hipStreamWaitEvent(s, T.ev_join, 0));
     prof_begin(T, ST_L2P, s);
+#define L2P_CALL(Tg, O)                                                 \
+  do {                                                                  \
+    if (p == P_FIXED)                                                   \
+      k_l2p_combine<R, Tg, O, P_FIXED><<<nchunks, 64, 0, s>>>(a);       \
+    else                                                                \
+      k_l2p_combine<R, Tg, O, 0><<<nchunks, 64, 0, s>>>(a);             \
+  } while (0)
     if (!tgt_ch) {
-      if (rq.out == OUT_NGRAD) k_l2p_combine<R, TGT_PANEL, OUT_NGRAD><<<nchunks, 64, 0, s>>>(a);
-      else k_l2p_combine<R, TGT_PANEL, OUT_POT><<<nchunks, 64, 0, s>>>(a);
+      if (rq.out == OUT_NGRAD) L2P_CALL(TGT_PANEL, OUT_NGRAD);
+      else L2P_CALL(TGT_PANEL, OUT_POT);
     } else {
-      if (rq.out == OUT_POTGRAD) k_l2p_combine<R, TGT_CHARGE, OUT_POTGRAD><<<nchunks, 64, 0, s>>>(a);
-      else k_l2p_combine<R, TGT_CHARGE, OUT_POT><<<nchunks, 64, 0, s>>>(a);
+      if (rq.out == OUT_POTGRAD) L2P_CALL(TGT_CHARGE, OUT_POTGRAD);
+      else L2P_CALL(TGT_CHARGE, OUT_POT);
     }
+#undef L2P_CALL
     LAUNCH_OK();
     prof_end(T, ST_L2P, s);
   }
