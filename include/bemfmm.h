@@ -41,9 +41,11 @@
  *   the cache, on first use): BEMFMM_CONCURRENT_P2P=0 runs the near field
  *   on `stream` after the multipole passes; BEMFMM_M2L_PERSISTENT=0 uses one
  *   workgroup per FP32 M2L tile instead of persistent workgroups;
- *   BEMFMM_CACHE_LIMIT_MB caps the device memory kept for reuse per device
- *   (default 32768, see bemfmm_release_cache).  Results do not depend on the
- *   first two.
+ *   BEMFMM_FORK_AT=0, 1 or 2 starts the near field at the start of the
+ *   product, after P2M or after M2M (default: after M2M in FP32, after P2M in
+ *   FP64); BEMFMM_CACHE_LIMIT_MB caps the device memory kept for reuse per
+ *   device (default 32768, see bemfmm_release_cache).  Results do not depend
+ *   on the first three.
  */
 #ifndef BEMFMM_H
 #define BEMFMM_H

@@ -31,6 +31,8 @@ constexpr int PMAX = 12;
 // expansion order with kernels specialised at compile time (the order the
 // method is run at, Section 4); other orders take the generic kernels
 constexpr int P_FIXED = 10;
+// points of the upward pass where the near field can fork to the second stream
+enum ForkAt { FORK_START = 0, FORK_AFTER_P2M = 1, FORK_AFTER_M2M = 2 };
 // M2L work tiles: 4 waves x RT row tiles of 16 pairs
 constexpr int M2L_RT32 = 4, M2L_RT64 = 2;
 constexpr int M2L_ROWS32 = 4 * M2L_RT32 * 16, M2L_ROWS64 = 4 * M2L_RT64 * 16;
@@ -234,6 +236,7 @@ struct Tree {
   hipStream_t side_stream = nullptr;
   bool concurrent = true;        // near field on the second stream
   bool m2l_persistent = true;    // FP32 M2L: persistent workgroups (else one tile per workgroup)
+  int fork_at = -1;              // where the near field forks: a ForkAt value, -1 = per precision
   int n_cu = 256;                // compute units of the device
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool prof = false;

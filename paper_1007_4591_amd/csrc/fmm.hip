@@ -1287,9 +1287,6 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     LAUNCH_OK();
   }
   prof_end(T, ST_OTHER, s);
-  // near field on the side stream, concurrent with the multipole passes on
-  // the caller's stream; joined before L2P
-  HIP_OK(hipEventRecord(T.ev_fork, s));
   P2PArgs a{};
   a.p = p;
   a.ps = ps;
@@ -1318,41 +1315,50 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   a.dbg_far = B.dbg_far.p;
   a.near_out = B.near_out.p;
   B.last_tgt = rq.tgt;
-  // The near field runs on the second stream beside P2M-M2M: those passes
-  // leave most of the chip idle (few cells per level, LDS-bound P2M).
+  // The near field runs on the second stream, forked from the caller's
+  // stream at a point of the upward pass and joined before L2P.  FP32 forks
+  // after M2M: the M2L workgroups (most of a SIMD's registers) then start
+  // before near-field waves fill the chip, and the near field takes the
+  // rest.  FP64 forks after P2M.
   const hipStream_t ss = T.concurrent ? T.side_stream : s;
-  if (nchunks > 0) {
-    HIP_OK(hipStreamWaitEvent(ss, T.ev_fork, 0));
-    const P2PArgs &ap = a;
-    const unsigned nb = (unsigned)nchunks;
-    prof_begin(T, ST_P2P, ss);
-#define P2P_CALL(S, Tg, O) k_p2p_near<R, S, Tg, O><<<nb, 64, 0, ss>>>(ap)
-    if (!tgt_ch) {
-      if (rq.src == SRC_PANEL_MONO && rq.out == OUT_NGRAD) P2P_CALL(SRC_PANEL_MONO, TGT_PANEL, OUT_NGRAD);
-      else if (rq.src == SRC_PANEL_DIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_DIP, TGT_PANEL, OUT_POT);
-      else if (rq.src == SRC_CHARGE_MONO && rq.out == OUT_NGRAD) P2P_CALL(SRC_CHARGE_MONO, TGT_PANEL, OUT_NGRAD);
-      else if (rq.src == SRC_CHARGE_MONO && rq.out == OUT_POT) P2P_CALL(SRC_CHARGE_MONO, TGT_PANEL, OUT_POT);
-      else BF_THROW(BEMFMM_EINVAL, "unsupported FMM request (panel targets)");
-    } else {
-      if (rq.src == SRC_PANEL_MONO && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_MONO, TGT_CHARGE, OUT_POT);
-      else if (rq.src == SRC_PANEL_DIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_DIP, TGT_CHARGE, OUT_POT);
-      else if (rq.src == SRC_PANEL_MONODIP && rq.out == OUT_POTGRAD) P2P_CALL(SRC_PANEL_MONODIP, TGT_CHARGE, OUT_POTGRAD);
-      else if (rq.src == SRC_PANEL_MONODIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_MONODIP, TGT_CHARGE, OUT_POT);
-      else BF_THROW(BEMFMM_EINVAL, "unsupported FMM request (charge targets)");
-    }
-#undef P2P_CALL
-    LAUNCH_OK();
-    prof_end(T, ST_P2P, ss);
-    HIP_OK(hipEventRecord(T.ev_join, ss));
-  }
-
   const int combo = src_charges ? 1 : (rq.tgt == TGT_CHARGE ? 2 : 0);
   const Tree::M2LList &ML = T.m2l[combo];
   const bool far = (L >= 2) && T.nfar > 0;
+  const int fork_at = !far ? FORK_START : T.fork_at >= 0 ? T.fork_at : (f64 ? FORK_AFTER_P2M : FORK_AFTER_M2M);
+  auto fork_near = [&]() {
+    HIP_OK(hipEventRecord(T.ev_fork, s));
+    if (nchunks > 0) {
+      HIP_OK(hipStreamWaitEvent(ss, T.ev_fork, 0));
+      const P2PArgs &ap = a;
+      const unsigned nb = (unsigned)nchunks;
+      prof_begin(T, ST_P2P, ss);
+#define P2P_CALL(S, Tg, O) k_p2p_near<R, S, Tg, O><<<nb, 64, 0, ss>>>(ap)
+      if (!tgt_ch) {
+        if (rq.src == SRC_PANEL_MONO && rq.out == OUT_NGRAD) P2P_CALL(SRC_PANEL_MONO, TGT_PANEL, OUT_NGRAD);
+        else if (rq.src == SRC_PANEL_DIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_DIP, TGT_PANEL, OUT_POT);
+        else if (rq.src == SRC_CHARGE_MONO && rq.out == OUT_NGRAD) P2P_CALL(SRC_CHARGE_MONO, TGT_PANEL, OUT_NGRAD);
+        else if (rq.src == SRC_CHARGE_MONO && rq.out == OUT_POT) P2P_CALL(SRC_CHARGE_MONO, TGT_PANEL, OUT_POT);
+        else BF_THROW(BEMFMM_EINVAL, "unsupported FMM request (panel targets)");
+      } else {
+        if (rq.src == SRC_PANEL_MONO && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_MONO, TGT_CHARGE, OUT_POT);
+        else if (rq.src == SRC_PANEL_DIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_DIP, TGT_CHARGE, OUT_POT);
+        else if (rq.src == SRC_PANEL_MONODIP && rq.out == OUT_POTGRAD) P2P_CALL(SRC_PANEL_MONODIP, TGT_CHARGE, OUT_POTGRAD);
+        else if (rq.src == SRC_PANEL_MONODIP && rq.out == OUT_POT) P2P_CALL(SRC_PANEL_MONODIP, TGT_CHARGE, OUT_POT);
+        else BF_THROW(BEMFMM_EINVAL, "unsupported FMM request (charge targets)");
+      }
+#undef P2P_CALL
+      LAUNCH_OK();
+      prof_end(T, ST_P2P, ss);
+      HIP_OK(hipEventRecord(T.ev_join, ss));
+    }
+  };
+  if (fork_at == FORK_START) fork_near();
+
   if (far) {
     prof_begin(T, ST_P2M, s);
     launch_p2m<R>(T, B, rq.src, s);
     prof_end(T, ST_P2M, s);
+    if (fork_at == FORK_AFTER_P2M) fork_near();
     // M2M, parents of levels L-1 .. 2: a batched MFMA product per child level
     // (one row per child), then each parent adds its children's rows
     prof_begin(T, ST_M2M, s);
@@ -1365,6 +1371,7 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
       LAUNCH_OK();
     }
     prof_end(T, ST_M2M, s);
+    if (fork_at == FORK_AFTER_M2M) fork_near();
   }
   if (far) {
     // M2L, every level in one launch
@@ -1463,6 +1470,7 @@ void fmm_apply(Tree &T, int precision, const FmmRequest &rq, hipStream_t s) {
     T.ev_init = true;
     if (const char *e = getenv("BEMFMM_CONCURRENT_P2P")) T.concurrent = atoi(e) != 0;
     if (const char *e = getenv("BEMFMM_M2L_PERSISTENT")) T.m2l_persistent = atoi(e) != 0;
+    if (const char *e = getenv("BEMFMM_FORK_AT")) T.fork_at = std::min(std::max(atoi(e), -1), (int)FORK_AFTER_M2M);
     int dev = 0;
     HIP_OK(hipGetDevice(&dev));
     HIP_OK(hipDeviceGetAttribute(&T.n_cu, hipDeviceAttributeMultiprocessorCount, dev));

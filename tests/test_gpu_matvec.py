@@ -93,17 +93,19 @@ def test_fmm_deterministic():
     np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("order", [10, 8])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 2e-6)])
-def test_expansions_match_definitions(prec, tol):
+def test_expansions_match_definitions(prec, tol, order):
     """Multipole expansions of every cell (P2M at the leaves, M2M above)
     equal the definition M_n^m = sum w conj(R_n^m(y - X)) applied directly
-    to the cell's sources (M2M is exact), element by element."""
+    to the cell's sources (M2M is exact), element by element.  p = 10 runs
+    the P2M compiled for that order, p = 8 the generic one."""
     B = lib()
     p = synth.blobby(4)
     g = oracle.geometry(p.verts, p.tris)
     rng = np.random.default_rng(3)
     x = rng.normal(size=p.n_panels)
-    t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params(ncrit=16))
+    t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params(ncrit=16, p=order))
     B.fmm_matvec(t, 0, prec, dev(x))
     Mg = B.debug_expansions(t, prec, 0)
     ex = B.tree_export(t)
@@ -123,7 +125,7 @@ def test_expansions_match_definitions(prec, tol):
             if e == b:
                 continue
             idx = perm[b:e]
-            want = H.p2m(g.c[idx], w[idx], X, s, 10)
+            want = H.p2m(g.c[idx], w[idx], X, s, order)
             scale = np.abs(want).max()
             err = np.abs(Mg[c] - want).max() / scale
             assert err <= tol, (l, c, err)
@@ -196,20 +198,23 @@ def test_rebuild_after_destroy_reuses_memory_bitwise():
 
 
 def test_switches_do_not_change_results(monkeypatch):
-    """The near field run concurrently or after the multipole passes, and the
-    FP32 M2L with persistent or one-tile workgroups, give bitwise the same
-    products (the switches change scheduling, not arithmetic)."""
+    """The near field run concurrently (forked at any point of the upward
+    pass) or after the multipole passes, and the FP32 M2L with persistent or
+    one-tile workgroups, give bitwise the same products (the switches change
+    scheduling, not arithmetic)."""
     B = lib()
     p = synth.blobby(5)
     x, y, qv = _inputs(p)
     outs = {}
-    for conc, pers in (("1", "1"), ("0", "1"), ("1", "0")):
+    for conc, pers, fork in (("1", "1", "-1"), ("0", "1", "-1"), ("1", "0", "-1"), ("1", "1", "0"), ("1", "1", "1"),
+                             ("1", "1", "2")):
         monkeypatch.setenv("BEMFMM_CONCURRENT_P2P", conc)
         monkeypatch.setenv("BEMFMM_M2L_PERSISTENT", pers)
+        monkeypatch.setenv("BEMFMM_FORK_AT", fork)
         t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params())
-        outs[(conc, pers)] = {prec: _run_all(B, t, x, y, qv, prec) for prec in (0, 1)}
+        outs[(conc, pers, fork)] = {prec: _run_all(B, t, x, y, qv, prec) for prec in (0, 1)}
         B.tree_destroy(t)
-    ref = outs[("1", "1")]
+    ref = outs[("1", "1", "-1")]
     for key, o in outs.items():
         for prec in (0, 1):
             for op in range(6):
