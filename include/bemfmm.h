@@ -42,10 +42,10 @@
  *   on `stream` after the multipole passes; BEMFMM_M2L_PERSISTENT=0 uses one
  *   workgroup per FP32 M2L tile instead of persistent workgroups;
  *   BEMFMM_FORK_AT=0, 1 or 2 starts the near field at the start of the
- *   product, after P2M or after M2M (default: after M2M in FP32, after P2M in
- *   FP64); BEMFMM_CACHE_LIMIT_MB caps the device memory kept for reuse per
- *   device (default 32768, see bemfmm_release_cache).  Results do not depend
- *   on the first three.
+ *   product, after P2M or after M2M (default: after M2M for an FP32 M2L of
+ *   at least 32 tiles per compute unit, else after P2M); BEMFMM_CACHE_LIMIT_MB caps the device memory kept for reuse per
+ *   device (default: half of the device's memory, see
+ *   bemfmm_release_cache).  Results do not depend on the first three.
  */
 #ifndef BEMFMM_H
 #define BEMFMM_H
@@ -194,10 +194,11 @@ const char *bemfmm_last_error(void);
 
 /* Device memory of destroyed trees and of grown workspaces is kept by the
  * library, per device, and reused by later builds of a similar size (up to
- * BEMFMM_CACHE_LIMIT_MB per device, default 32768; a failed allocation
- * empties the cache and retries).  This call returns every cached block of
- * every device to the driver after synchronising each device; memory of
- * live trees is untouched. */
+ * BEMFMM_CACHE_LIMIT_MB per device, default half of the device's memory; a
+ * failed allocation of the library empties the cache and retries).  Other
+ * allocators in the process (PyTorch's) do not see this memory as free:
+ * this call returns every cached block of every device to the driver after
+ * synchronising each device; memory of live trees is untouched. */
 int bemfmm_release_cache(void);
 
 /* ----------------------------------------------------------------------

@@ -31,19 +31,28 @@ struct DevCache {
   std::multimap<size_t, void *> ready;    // size -> block, safe to reuse
   std::vector<std::pair<size_t, void *>> pending;  // freed, maybe still in use
   size_t cached_bytes = 0;                // ready + pending
+  size_t limit = 0;                       // upper bound of cached_bytes; 0 = not set yet
 };
 
 struct Cache {
   std::mutex mu;
   std::unordered_map<void *, std::pair<int, size_t>> live;  // block -> (device, size)
   std::map<int, DevCache> dev;
-  size_t limit = 0;
-  Cache() {
-    // upper bound of the bytes kept cached per device
-    const char *e = getenv("BEMFMM_CACHE_LIMIT_MB");
-    limit = (e ? (size_t)atoll(e) : (size_t)32768) << 20;
-  }
 };
+
+// Bytes a device keeps cached at most: BEMFMM_CACHE_LIMIT_MB, else half of
+// the device's memory.  A large tree (10^7 panels) holds about 100 GB, and
+// returning blocks of that size to the driver can stall for a second, so the
+// default keeps a whole tree's worth for the next build.
+size_t cache_limit() {
+  if (const char *e = getenv("BEMFMM_CACHE_LIMIT_MB")) return (size_t)atoll(e) << 20;
+  size_t fr = 0, total = 0;
+  if (hipMemGetInfo(&fr, &total) != hipSuccess) {
+    (void)hipGetLastError();
+    return (size_t)32768 << 20;
+  }
+  return total / 2;
+}
 
 Cache &cache() {
   static Cache *c = new Cache();  // never destroyed: blocks live until exit
@@ -69,6 +78,7 @@ void *dev_alloc(size_t bytes) {
   Cache &c = cache();
   std::lock_guard<std::mutex> lk(c.mu);
   DevCache &d = c.dev[device];
+  if (!d.limit) d.limit = cache_limit();
   // best fit among blocks of at most 1/8 more than requested
   const size_t slack = sz / 8;
   auto take = [&](void) -> void * {
@@ -118,7 +128,7 @@ void dev_free(void *p) noexcept {
   const size_t sz = it->second.second;
   c.live.erase(it);
   DevCache &d = c.dev[device];
-  if (d.cached_bytes + sz > c.limit) {
+  if (d.cached_bytes + sz > d.limit) {
     (void)hipFree(p);  // waits for the device like any hipFree
     return;
   }

@@ -1316,15 +1316,18 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   a.near_out = B.near_out.p;
   B.last_tgt = rq.tgt;
   // The near field runs on the second stream, forked from the caller's
-  // stream at a point of the upward pass and joined before L2P.  FP32 forks
-  // after M2M: the M2L workgroups (most of a SIMD's registers) then start
-  // before near-field waves fill the chip, and the near field takes the
-  // rest.  FP64 forks after P2M.
+  // stream at a point of the upward pass and joined before L2P.  It forks
+  // after P2M, except for an FP32 M2L large enough to keep its persistent
+  // workgroups busy for a while (at least 32 tiles per CU): that forks after
+  // M2M, so that the M2L workgroups (most of a SIMD's registers) are
+  // resident before near-field waves fill the chip, and the near field takes
+  // the rest.
   const hipStream_t ss = T.concurrent ? T.side_stream : s;
   const int combo = src_charges ? 1 : (rq.tgt == TGT_CHARGE ? 2 : 0);
   const Tree::M2LList &ML = T.m2l[combo];
   const bool far = (L >= 2) && T.nfar > 0;
-  const int fork_at = !far ? FORK_START : T.fork_at >= 0 ? T.fork_at : (f64 ? FORK_AFTER_P2M : FORK_AFTER_M2M);
+  const bool big_m2l = !f64 && T.m2l_persistent && ML.ntiles >= 32 * (int64_t)T.n_cu;
+  const int fork_at = !far ? FORK_START : T.fork_at >= 0 ? T.fork_at : (big_m2l ? FORK_AFTER_M2M : FORK_AFTER_P2M);
   auto fork_near = [&]() {
     HIP_OK(hipEventRecord(T.ev_fork, s));
     if (nchunks > 0) {

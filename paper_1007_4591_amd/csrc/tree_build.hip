@@ -61,9 +61,10 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_reduce(const int32_t *__res
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// `in` and `out` may alias (each thread reads its items before writing them)
+// `in` and `out` may alias (each thread reads its items before writing them);
+// the last block also writes the scan's total to `total` when non-NULL
 __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(const int32_t *in, int64_t n, const int32_t *offs,
-                                                           int32_t *out) {
+                                                           int32_t *out, int32_t *total) {
   int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   int32_t v[SCAN_ITEMS];
   int32_t s = 0;
@@ -73,48 +74,43 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(const int32_t *in, in
     s += v[k];
   }
   int32_t tot;
-  int32_t run = block_exclusive_scan(s, &tot) + (offs ? offs[blockIdx.x] : 0);
+  const int32_t off = offs ? offs[blockIdx.x] : 0;
+  int32_t run = block_exclusive_scan(s, &tot) + off;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
     if (base + k < n) out[base + k] = run;
     run += v[k];
   }
+  if (total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = off + tot;
 }
 
-}  // namespace
-
-namespace {
-// total of a scan from its block sums
-__global__ void k_scan_total(const int32_t *__restrict__ sums, const int32_t *__restrict__ sums_scan, int nb,
-                             int32_t *__restrict__ tot) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *tot = nb > 1 ? sums_scan[nb - 1] + sums[nb - 1] : sums[0];
-}
 }  // namespace
 
 // Exclusive prefix sum of n int32 values (out may alias in); the total is
 // returned through total_host when non-NULL (one stream synchronisation).
-// Without a total nothing waits: temporary buffers go back to the caching
-// allocator, which synchronises before it reuses them.
+// One launch when n fits one block; otherwise block sums, their scan (one
+// launch up to 2048 blocks) and the apply pass.  Without a total nothing
+// waits: temporary buffers go back to the caching allocator, which
+// synchronises before it reuses them.
 void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, int32_t *total_host) {
   if (n <= 0) {
     if (total_host) *total_host = 0;
     return;
   }
-  int nb = cdiv(n, SCAN_TILE);
+  const int nb = cdiv(n, SCAN_TILE);
   DBuf<int32_t> sums, sums_scan;
-  sums.alloc(nb + 1);
-  k_scan_reduce<<<nb, SCAN_BLOCK, 0, s>>>(in, n, sums.p);
-  LAUNCH_OK();
+  sums.alloc(nb + 1);  // block sums, then the total
+  int32_t *tot_dev = total_host ? sums.p + nb : nullptr;
   if (nb > 1) {
-    sums_scan.alloc(nb + 1);
+    k_scan_reduce<<<nb, SCAN_BLOCK, 0, s>>>(in, n, sums.p);
+    LAUNCH_OK();
+    sums_scan.alloc(nb);
     exclusive_scan_i32(sums.p, sums_scan.p, nb, s, nullptr);
   }
-  k_scan_apply<<<nb, SCAN_BLOCK, 0, s>>>(in, n, nb > 1 ? sums_scan.p : nullptr, out);
+  k_scan_apply<<<nb, SCAN_BLOCK, 0, s>>>(in, n, nb > 1 ? sums_scan.p : nullptr, out, tot_dev);
   LAUNCH_OK();
   if (total_host) {
-    k_scan_total<<<1, 1, 0, s>>>(sums.p, nb > 1 ? sums_scan.p : nullptr, nb, sums.p + nb);
-    LAUNCH_OK();
-    HIP_OK(hipMemcpyAsync(total_host, sums.p + nb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(total_host, tot_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
   }
 }
