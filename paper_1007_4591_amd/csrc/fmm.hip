@@ -783,12 +783,39 @@ __device__ __forceinline__ void pair_eval(const typename V4<R>::T &s4, const typ
   }
 }
 
+
+
+// A pair from r^2; `skip` marks the excluded self pair (its terms are zero).
+// FP64 monopole sources with only the normal derivative wanted (the A and B
+// products) need w/r^3 alone: with y0 the hardware estimate of r^-1/2 and
+// e = 1 - r^2 y0^2, the Newton-corrected 1/r^3 is y0^3 (1 + 3e/2) to first
+// order in e, one multiply fewer than correcting 1/r and cubing it.
+template <class R, int SRC, int OUT>
+__device__ __forceinline__ void pair_eval_r2(const typename V4<R>::T &s4, const typename V4<R>::T &m4, R dx, R dy,
+                                             R dz, R r2, bool skip, R &lp, R &lx, R &ly, R &lz) {
+  if constexpr (std::is_same<R, double>::value && (SRC == SRC_PANEL_MONO || SRC == SRC_CHARGE_MONO) &&
+                OUT == OUT_NGRAD) {
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double y2 = y0 * y0;
+    const double e = __builtin_fma(-r2, y2, 1.0);
+    const double y3 = y2 * y0;
+    double t = s4.w * __builtin_fma(1.5 * y3, e, y3);
+    if (skip) t = 0.0;
+    lx += t * dx;
+    ly += t * dy;
+    lz += t * dz;
+  } else {
+    const R ri = skip ? R(0) : rsq(r2);
+    pair_eval<R, SRC, OUT>(s4, m4, dx, dy, dz, ri, lp, lx, ly, lz);
+  }
+}
+
 template <class R, int SRC, int OUT>
 __device__ __forceinline__ void pair_accumulate(const typename V4<R>::T &s4, const typename V4<R>::T *sdip, int j,
-                                                R dx, R dy, R dz, R ri, R &lp, R &lx, R &ly, R &lz) {
+                                                R dx, R dy, R dz, R r2, bool skip, R &lp, R &lx, R &ly, R &lz) {
   typename V4<R>::T m4{};
   if (SRC == SRC_PANEL_DIP || SRC == SRC_PANEL_MONODIP) m4 = sdip[j];
-  pair_eval<R, SRC, OUT>(s4, m4, dx, dy, dz, ri, lp, lx, ly, lz);
+  pair_eval_r2<R, SRC, OUT>(s4, m4, dx, dy, dz, r2, skip, lp, lx, ly, lz);
 }
 
 struct P2PArgs {
@@ -868,8 +895,8 @@ __global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
           const R4 s4 = spos[j];
           const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
           const R r2 = dx * dx + dy * dy + dz * dz;
-          const R ri = (j == ti) ? R(0) : rsq(r2);  // K'_ii = 0: the self panel is skipped by index
-          pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
+          // K'_ii = 0: the self panel is skipped by index
+          pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, r2, j == ti, lp, lx, ly, lz);
         }
       } else {
         // software pipelined: the records of the next PF sources are
@@ -896,7 +923,7 @@ __global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
             for (int u = 0; u < PF; ++u) {
               const R dx = ux - cs[u].x, dy = uy - cs[u].y, dz = uz - cs[u].z;
               const R r2 = dx * dx + dy * dy + dz * dz;
-              pair_eval<R, SRC, OUT>(cs[u], cm[u], dx, dy, dz, rsq(r2), lp, lx, ly, lz);
+              pair_eval_r2<R, SRC, OUT>(cs[u], cm[u], dx, dy, dz, r2, false, lp, lx, ly, lz);
             }
 #pragma unroll
             for (int u = 0; u < PF; ++u) {
@@ -908,7 +935,7 @@ __global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
           for (int u = 0; u < PF; ++u) {
             const R dx = ux - cs[u].x, dy = uy - cs[u].y, dz = uz - cs[u].z;
             const R r2 = dx * dx + dy * dy + dz * dz;
-            pair_eval<R, SRC, OUT>(cs[u], cm[u], dx, dy, dz, rsq(r2), lp, lx, ly, lz);
+            pair_eval_r2<R, SRC, OUT>(cs[u], cm[u], dx, dy, dz, r2, false, lp, lx, ly, lz);
           }
           j += PF;
         }
@@ -916,8 +943,7 @@ __global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
           const R4 s4 = spos[j];
           const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
           const R r2 = dx * dx + dy * dy + dz * dz;
-          const R ri = rsq(r2);
-          pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, ri, lp, lx, ly, lz);
+          pair_accumulate<R, SRC, OUT>(s4, sdip, j, dx, dy, dz, r2, false, lp, lx, ly, lz);
         }
       }
     } else {
@@ -939,8 +965,7 @@ __global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
             const R4 s4 = src_s[jj];
             const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
             const R r2 = dx * dx + dy * dy + dz * dz;
-            const R ri = (base + jj == ti) ? R(0) : rsq(r2);
-            pair_eval<R, SRC, OUT>(s4, DIPS ? dip_s[jj] : s4, dx, dy, dz, ri, lp, lx, ly, lz);
+            pair_eval_r2<R, SRC, OUT>(s4, DIPS ? dip_s[jj] : s4, dx, dy, dz, r2, base + jj == ti, lp, lx, ly, lz);
           }
         } else {
 #pragma unroll 4
@@ -948,7 +973,7 @@ __global__ void __launch_bounds__(64) k_p2p_near(P2PArgs a) {
             const R4 s4 = src_s[jj];
             const R dx = ux - s4.x, dy = uy - s4.y, dz = uz - s4.z;
             const R r2 = dx * dx + dy * dy + dz * dz;
-            pair_eval<R, SRC, OUT>(s4, DIPS ? dip_s[jj] : s4, dx, dy, dz, rsq(r2), lp, lx, ly, lz);
+            pair_eval_r2<R, SRC, OUT>(s4, DIPS ? dip_s[jj] : s4, dx, dy, dz, r2, false, lp, lx, ly, lz);
           }
         }
       }
