@@ -785,25 +785,34 @@ __device__ __forceinline__ void pair_eval(const typename V4<R>::T &s4, const typ
 
 
 
+// 1/r^3 in FP64 from r^2 without forming 1/r: with y0 the hardware estimate
+// of r^-1/2 and e = 1 - r^2 y0^2, the Newton-corrected 1/r^3 is
+// y0^3 (1 + 3e/2) to first order in e, one multiply fewer than correcting
+// 1/r and cubing it.
+__device__ __forceinline__ double inv_r3(double r2) {
+  const double y0 = __builtin_amdgcn_rsq(r2);
+  const double y2 = y0 * y0;
+  const double e = __builtin_fma(-r2, y2, 1.0);
+  const double y3 = y2 * y0;
+  return __builtin_fma(1.5 * y3, e, y3);
+}
+
 // A pair from r^2; `skip` marks the excluded self pair (its terms are zero).
-// FP64 monopole sources with only the normal derivative wanted (the A and B
-// products) need w/r^3 alone: with y0 the hardware estimate of r^-1/2 and
-// e = 1 - r^2 y0^2, the Newton-corrected 1/r^3 is y0^3 (1 + 3e/2) to first
-// order in e, one multiply fewer than correcting 1/r and cubing it.
+// In FP64 the pairs that need only 1/r^3 take it from inv_r3: monopole
+// sources with the normal derivative (the A and B products) and dipole
+// sources with the potential (the A^T product).
 template <class R, int SRC, int OUT>
 __device__ __forceinline__ void pair_eval_r2(const typename V4<R>::T &s4, const typename V4<R>::T &m4, R dx, R dy,
                                              R dz, R r2, bool skip, R &lp, R &lx, R &ly, R &lz) {
-  if constexpr (std::is_same<R, double>::value && (SRC == SRC_PANEL_MONO || SRC == SRC_CHARGE_MONO) &&
-                OUT == OUT_NGRAD) {
-    const double y0 = __builtin_amdgcn_rsq(r2);
-    const double y2 = y0 * y0;
-    const double e = __builtin_fma(-r2, y2, 1.0);
-    const double y3 = y2 * y0;
-    double t = s4.w * __builtin_fma(1.5 * y3, e, y3);
-    if (skip) t = 0.0;
+  constexpr bool F64 = std::is_same<R, double>::value;
+  if constexpr (F64 && (SRC == SRC_PANEL_MONO || SRC == SRC_CHARGE_MONO) && OUT == OUT_NGRAD) {
+    const double t = skip ? 0.0 : s4.w * inv_r3(r2);
     lx += t * dx;
     ly += t * dy;
     lz += t * dz;
+  } else if constexpr (F64 && SRC == SRC_PANEL_DIP && OUT == OUT_POT) {
+    const double ri3 = skip ? 0.0 : inv_r3(r2);
+    lp += (m4.x * dx + m4.y * dy + m4.z * dz) * ri3;
   } else {
     const R ri = skip ? R(0) : rsq(r2);
     pair_eval<R, SRC, OUT>(s4, m4, dx, dy, dz, ri, lp, lx, ly, lz);
