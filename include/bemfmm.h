@@ -21,7 +21,10 @@
  * ---------------------------------------
  * - Arrays are DEVICE pointers (memory of the current HIP device), FP64, in
  *   the caller's original order, row-major (x,y,z) for 3-vectors, unless the
- *   argument name ends in _host.  The caller owns every argument buffer;
+ *   argument name ends in _host.  A tree lives on the device that was
+ *   current when it was built; calls on it run there (the library makes
+ *   that device current for the call and restores the caller's), so their
+ *   arrays and stream must belong to that device.  The caller owns every argument buffer;
  *   the library copies what it keeps, so inputs may be freed after a call.
  * - All device work is enqueued on `stream` (a hipStream_t; NULL is the
  *   null stream).  Entry points that return host scalars or solve iteratively
@@ -43,9 +46,10 @@
  *   workgroup per FP32 M2L tile instead of persistent workgroups;
  *   BEMFMM_FORK_AT=0, 1 or 2 starts the near field at the start of the
  *   product, after P2M or after M2M (default: after M2M for an FP32 M2L of
- *   at least 32 tiles per compute unit, else after P2M); BEMFMM_CACHE_LIMIT_MB caps the device memory kept for reuse per
- *   device (default: half of the device's memory, see
- *   bemfmm_release_cache).  Results do not depend on the first three.
+ *   at least 32 tiles per compute unit, else after P2M);
+ *   BEMFMM_CACHE_LIMIT_MB caps the device memory kept for reuse per device
+ *   (default: half of the device's memory, see bemfmm_release_cache).
+ *   Results do not depend on the first three.
  */
 #ifndef BEMFMM_H
 #define BEMFMM_H

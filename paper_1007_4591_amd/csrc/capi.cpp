@@ -31,6 +31,21 @@ Tree *check_tree(const bemfmm_tree *t) {
   return T;
 }
 
+// Makes the tree's device current for the duration of an entry point and
+// restores the caller's device afterwards.
+struct DeviceScope {
+  int prev = -1, want = 0;
+  explicit DeviceScope(const Tree &T) : want(T.device) {
+    HIP_OK(hipGetDevice(&prev));
+    if (prev != want) HIP_OK(hipSetDevice(want));
+  }
+  ~DeviceScope() {
+    if (prev >= 0 && prev != want) (void)hipSetDevice(prev);
+  }
+  DeviceScope(const DeviceScope &) = delete;
+  DeviceScope &operator=(const DeviceScope &) = delete;
+};
+
 template <class F>
 static int guard(F &&f) {
   g_err.clear();
@@ -94,6 +109,7 @@ int bemfmm_build_tree(const double *verts, int64_t nv, const int32_t *tris, int6
 int bemfmm_set_charges(bemfmm_tree *tree, const double *charge_pos, void *stream) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     need(T->Q == 0 || charge_pos, "charge_pos is NULL");
     set_charges(*T, charge_pos, (hipStream_t)stream);
   });
@@ -102,6 +118,7 @@ int bemfmm_set_charges(bemfmm_tree *tree, const double *charge_pos, void *stream
 int bemfmm_tree_destroy(bemfmm_tree *tree) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     (void)hipDeviceSynchronize();
     delete T;
   });
@@ -110,6 +127,7 @@ int bemfmm_tree_destroy(bemfmm_tree *tree) {
 int bemfmm_tree_get_info(const bemfmm_tree *tree, bemfmm_tree_info *info) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     need(info != nullptr, "info is NULL");
     bemfmm_tree_info I{};
     I.n_panels = T->N;
@@ -131,6 +149,7 @@ int bemfmm_tree_get_info(const bemfmm_tree *tree, bemfmm_tree_info *info) {
 int bemfmm_fmm_matvec(bemfmm_tree *tree, int op, int precision, const double *x, double *y, void *stream) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     need(op >= BEMFMM_OP_A && op <= BEMFMM_OP_CT, "unknown operator");
     need(precision >= BEMFMM_FP64 && precision <= BEMFMM_FP32_REFINED, "unknown precision");
     need(x && y, "x/y are NULL");
@@ -142,6 +161,7 @@ int bemfmm_solve_bem(bemfmm_tree *tree, const double *q, double *x, double tol, 
                      int precision, bemfmm_solve_info *info, void *stream) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     need(precision >= BEMFMM_FP64 && precision <= BEMFMM_FP32_REFINED, "unknown precision");
     need(x != nullptr && (T->Q == 0 || q != nullptr), "q/x are NULL");
     need(tol > 0 && maxit >= 1, "tol must be > 0 and maxit >= 1");
@@ -153,6 +173,7 @@ int bemfmm_bibee_energy(bemfmm_tree *tree, const double *q, int kind, int precis
                         void *stream) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     need(kind == BEMFMM_BIBEE_CFA || kind == BEMFMM_BIBEE_P, "unknown BIBEE kind");
     need(dG_host != nullptr && (T->Q == 0 || q != nullptr), "q/dG are NULL");
     *dG_host = bibee(*T, q, kind, precision, (hipStream_t)stream);
@@ -163,6 +184,7 @@ int bemfmm_solvation_energy(bemfmm_tree *tree, const double *q, const double *x,
                             void *stream) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     need(dG_host != nullptr && x != nullptr && (T->Q == 0 || q != nullptr), "q/x/dG are NULL");
     *dG_host = energy(*T, q, x, precision, (hipStream_t)stream);
   });
@@ -172,6 +194,7 @@ int bemfmm_adjoint_grad(bemfmm_tree *tree, const double *q, const double *x, dou
                         int precision, double *dG_dq, double *dG_dpos, bemfmm_solve_info *info, void *stream) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     need(x != nullptr && (T->Q == 0 || q != nullptr), "q/x are NULL");
     need(tol > 0 && maxit >= 1, "tol must be > 0 and maxit >= 1");
     adjoint(*T, q, x, tol, maxit, restart, precision, dG_dq, dG_dpos, info, (hipStream_t)stream);
@@ -189,6 +212,7 @@ int bemfmm_tree_export(const bemfmm_tree *tree, int32_t *panel_perm, int32_t *ch
                        int32_t *cell_parent, int32_t *near_ptr, int32_t *near_idx, int32_t *far_pairs) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     const int L = T->L;
     auto d2h = [&](void *dst, const void *src, size_t bytes) {
       if (dst && bytes) HIP_OK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
@@ -222,6 +246,7 @@ int bemfmm_tree_export(const bemfmm_tree *tree, int32_t *panel_perm, int32_t *ch
 int bemfmm_debug_expansions(bemfmm_tree *tree, int precision, int which, double *out_host) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     need(out_host != nullptr, "out is NULL");
     HIP_OK(hipDeviceSynchronize());
     debug_expansions(*T, precision, which, out_host, nullptr);
@@ -231,6 +256,7 @@ int bemfmm_debug_expansions(bemfmm_tree *tree, int precision, int which, double 
 int bemfmm_debug_fields(bemfmm_tree *tree, int precision, double *near_host, double *far_host) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     HIP_OK(hipDeviceSynchronize());
     debug_fields(*T, precision, near_host, far_host, nullptr);
   });
@@ -239,6 +265,7 @@ int bemfmm_debug_fields(bemfmm_tree *tree, int precision, double *near_host, dou
 int bemfmm_profile(bemfmm_tree *tree, int enable, int reset) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     T->prof = enable != 0;
     if (reset)
       for (auto &k : T->prof_ms)
@@ -254,6 +281,7 @@ int bemfmm_profile(bemfmm_tree *tree, int enable, int reset) {
 int bemfmm_profile_select(bemfmm_tree *tree, int op, int precision) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     need(op >= -1 && op < 6, "op must be -1 or a BEMFMM_OP_* value");
     need(precision == -1 || precision == BEMFMM_FP64 || precision == BEMFMM_FP32,
          "precision must be -1, BEMFMM_FP64 or BEMFMM_FP32");
@@ -265,6 +293,7 @@ int bemfmm_profile_select(bemfmm_tree *tree, int op, int precision) {
 int bemfmm_profile_get(bemfmm_tree *tree, const char *stage, double *ms_host, int64_t *count_host) {
   return guard([&] {
     Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
     need(stage != nullptr, "stage is NULL");
     static const char *names[7] = {"p2m", "m2m", "m2l", "l2l", "p2p", "other", "l2p"};
     // "name" (every product) or "name/op/precision" (one operator, FP64 = 0 or FP32 = 1)

@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
+#include <set>
 #include <type_traits>
 
 #include "common.h"
@@ -1119,10 +1121,15 @@ __global__ void __launch_bounds__(64) k_l2p_combine(P2PArgs a) {
   }
 }
 
-template <class R>
+// Uploads the recurrence coefficients to the current device's constant
+// memory, once per device (constant memory is per device).
 void set_rec_constants() {
-  static bool done = false;
-  if (done) return;
+  static std::mutex mu;
+  static std::set<int> done;
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count(dev)) return;
   float r1f[PMAX + 1][PMAX + 1] = {}, r2f[PMAX + 1][PMAX + 1] = {}, hf[PMAX + 1] = {};
   double r1d[PMAX + 1][PMAX + 1] = {}, r2d[PMAX + 1][PMAX + 1] = {}, hd[PMAX + 1] = {};
   for (int n = 0; n <= PMAX; ++n)
@@ -1144,7 +1151,7 @@ void set_rec_constants() {
   HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(c_rec2_d), r2d, sizeof(r2d)));
   HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(c_half_inv_m_f), hf, sizeof(hf)));
   HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(c_half_inv_m_d), hd, sizeof(hd)));
-  done = true;
+  done.insert(dev);
 }
 
 }  // namespace
@@ -1293,7 +1300,7 @@ static void level_product(Tree &T, int l, const int32_t *src, const void *table,
 template <class R>
 static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   using R4 = typename V4<R>::T;
-  set_rec_constants<R>();
+  set_rec_constants();
   const bool f64 = std::is_same<R, double>::value;
   const int L = T.L, p = T.p, ps = T.ps;
   const int TB = 256;
