@@ -99,7 +99,7 @@ void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t 
   }
   const int nb = cdiv(n, SCAN_TILE);
   DBuf<int32_t> sums, sums_scan;
-  sums.alloc(nb + 1);  // block sums, then the total
+  if (nb > 1 || total_host) sums.alloc(nb + 1);  // block sums, then the total
   int32_t *tot_dev = total_host ? sums.p + nb : nullptr;
   if (nb > 1) {
     k_scan_reduce<<<nb, SCAN_BLOCK, 0, s>>>(in, n, sums.p);
