@@ -607,6 +607,107 @@ k_m2l_pers(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ t
   m2l_tiles<NT, RT>(tile_group, tile_row, group_off, group_end, src, dest, Tsw, M, out, ntiles, Bs);
 }
 
+// Persistent FP64 M2L, for large pair counts (on small ones one tile per
+// workgroup is faster).  The FP64 operator (100 KB at p = 10) leaves room in
+// LDS for one workgroup per CU, so the workgroup has 8 waves (two per SIMD,
+// each with RT = 2 row tiles: 256 rows per tile, the FP32 tile lists) and
+// walks a contiguous, XCD-aware range of tiles, reloading the operator only
+// when the offset group changes.  Per tile the arithmetic is that of
+// k_m2l<double, NT, 2, false, 0> (same operands, same K order), so results
+// are identical; the operator is read from LDS instead of from L2 at every
+// k-step.
+template <int NT>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+k_m2l_pers64(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ tile_row,
+             const int32_t *__restrict__ group_off, const int32_t *__restrict__ group_end,
+             const int32_t *__restrict__ src, const int32_t *__restrict__ dest, const double *__restrict__ Tsw,
+             const double *__restrict__ M, double *__restrict__ out, int ntiles) {
+  constexpr int RT = 2, NW = 8;
+  constexpr int PS = NT * 16;
+  constexpr int KK = PS / 4;
+  constexpr int TB2 = KK * NT * 32;  // double2 per operator
+  __shared__ double2 Bs[TB2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int nwg = gridDim.x;
+  const int wg = xcd_block(blockIdx.x, nwg);
+  const int t0 = (int)((int64_t)ntiles * wg / nwg), t1 = (int)((int64_t)ntiles * (wg + 1) / nwg);
+  if (t0 >= t1) return;  // uniform over the workgroup
+
+  struct TileIn {
+    int g, end, row0;
+  };
+  auto tile_in = [&](int t) {
+    TileIn v;
+    v.g = tile_group[t];
+    v.end = group_end[v.g];
+    v.row0 = tile_row[t] + wave * (16 * RT);
+    return v;
+  };
+  auto stage_b = [&](int g) {
+    const double2 *Bg = reinterpret_cast<const double2 *>(Tsw) + (size_t)group_off[g] * TB2;
+    for (int v = threadIdx.x; v < TB2; v += 64 * NW) Bs[v] = Bg[v];
+  };
+
+  double a[RT][KK];
+  int d[RT][4];
+  TileIn cur = tile_in(t0);
+  stage_b(cur.g);
+  __syncthreads();
+  for (int t = t0; t < t1; ++t) {
+    if (t > t0) {
+      const TileIn nxt = tile_in(t);
+      if (group_off[nxt.g] != group_off[cur.g]) {
+        __syncthreads();  // every wave is done with the current operator
+        stage_b(nxt.g);
+        __syncthreads();
+      }
+      cur = nxt;
+    }
+    // gather: a lane loads the K slice of its lane group of row i16 of each
+    // row tile, and the destinations of the rows it stores
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int sr = src[min(cur.row0 + rt * 16 + i16, cur.end - 1)];
+      const double2 *Ms = reinterpret_cast<const double2 *>(M + (size_t)sr * PS + kq * KK);
+#pragma unroll
+      for (int v = 0; v < KK / 2; ++v) {
+        const double2 q = Ms[v];
+        a[rt][2 * v] = q.x;
+        a[rt][2 * v + 1] = q.y;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d[rt][q] = dest[min(cur.row0 + rt * 16 + kq + 4 * q, cur.end - 1)];
+    }
+    if (cur.row0 >= cur.end) continue;
+    f64x4 acc[RT][NT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const double *B = reinterpret_cast<const double *>(Bs) + lane;
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) {
+        const double b = B[(kk * NT + ct) * 64];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt][kk], b, acc[rt][ct], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (cur.row0 + rt * 16 + kq + 4 * q < cur.end) {
+          double *o = out + (size_t)d[rt][q] * PS + i16;
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct) o[ct * 16] = acc[rt][ct][q];
+        }
+  }
+}
+
 // ----------------------------------------------------------- downward pass
 
 template <class R> struct VecT;
@@ -1358,16 +1459,17 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   B.last_tgt = rq.tgt;
   // The near field runs on the second stream, forked from the caller's
   // stream at a point of the upward pass and joined before L2P.  It forks
-  // after P2M, except for an FP32 M2L large enough to keep its persistent
-  // workgroups busy for a while (at least 32 tiles per CU): that forks after
-  // M2M, so that the M2L workgroups (most of a SIMD's registers) are
-  // resident before near-field waves fill the chip, and the near field takes
-  // the rest.
+  // after P2M, except for an M2L large enough to keep persistent workgroups
+  // busy for a while (at least 32 tiles of 256 pairs per CU): that M2L runs
+  // persistent (in FP64 too) and the fork comes after M2M, so that the M2L
+  // workgroups (most of a SIMD's registers) are resident before near-field
+  // waves fill the chip, and the near field takes the rest.  Smaller M2L
+  // runs one tile per workgroup in FP64.
   const hipStream_t ss = T.concurrent ? T.side_stream : s;
   const int combo = src_charges ? 1 : (rq.tgt == TGT_CHARGE ? 2 : 0);
   const Tree::M2LList &ML = T.m2l[combo];
   const bool far = (L >= 2) && T.nfar > 0;
-  const bool big_m2l = !f64 && T.m2l_persistent && ML.ntiles >= 32 * (int64_t)T.n_cu;
+  const bool big_m2l = T.m2l_persistent && ML.ntiles >= 32 * (int64_t)T.n_cu;
   const int fork_at = !far ? FORK_START : T.fork_at >= 0 ? T.fork_at : (big_m2l ? FORK_AFTER_M2M : FORK_AFTER_P2M);
   auto fork_near = [&]() {
     HIP_OK(hipEventRecord(T.ev_fork, s));
@@ -1424,7 +1526,11 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
     if (ML.n > 0) {
 #define M2L_CASE(nt)                                                                                           \
   case nt:                                                                                                     \
-    if (f64)                                                                                                   \
+    if (f64 && big_m2l)                                                                                        \
+      k_m2l_pers64<nt><<<dim3((unsigned)std::min<int64_t>(ML.ntiles, T.n_cu)), 512, 0, s>>>(                    \
+          ML.tile_group.p, ML.tile_row.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p, T.t_m2l64,      \
+          reinterpret_cast<const double *>(M), reinterpret_cast<double *>(m2l), (int)ML.ntiles);               \
+    else if (f64)                                                                                              \
       k_m2l<double, nt, M2L_RT64, false, 0><<<dim3((unsigned)ML.ntiles64), 256, 0, s>>>(                         \
           ML.tile_group64.p, ML.tile_row64.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p, T.t_m2l64,             \
           reinterpret_cast<const double *>(M), reinterpret_cast<double *>(m2l));                               \

@@ -219,3 +219,21 @@ def test_switches_do_not_change_results(monkeypatch):
         for prec in (0, 1):
             for op in range(6):
                 assert np.array_equal(o[prec][op], ref[prec][op]), (key, prec, op)
+
+
+def test_persistent_m2l_matches_per_tile_at_full_size(monkeypatch):
+    """At the bench surface (1.31M panels) the M2L is large enough to run
+    persistent in both precisions (and the near field forks after M2M); the
+    one-tile-per-workgroup kernels give bitwise the same products."""
+    B = lib()
+    p = synth.blobby(8)
+    x = np.random.default_rng(9).normal(size=p.n_panels)
+    outs = {}
+    for pers in ("1", "0"):
+        monkeypatch.setenv("BEMFMM_M2L_PERSISTENT", pers)
+        t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params())
+        assert t.info["n_m2l_panel_pairs"] > 32 * 256 * 256
+        outs[pers] = [host(B.fmm_matvec(t, op, prec, dev(x))) for op in (0, 1) for prec in (0, 1)]
+        B.tree_destroy(t)
+    for a, b in zip(outs["1"], outs["0"]):
+        assert np.array_equal(a, b)
