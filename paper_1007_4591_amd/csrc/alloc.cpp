@@ -31,7 +31,8 @@ struct DevCache {
   std::multimap<size_t, void *> ready;    // size -> block, safe to reuse
   std::vector<std::pair<size_t, void *>> pending;  // freed, maybe still in use
   size_t cached_bytes = 0;                // ready + pending
-  size_t limit = 0;                       // upper bound of cached_bytes; 0 = not set yet
+  size_t limit = 0;                       // upper bound of cached_bytes
+  bool limit_set = false;
 };
 
 struct Cache {
@@ -78,7 +79,10 @@ void *dev_alloc(size_t bytes) {
   Cache &c = cache();
   std::lock_guard<std::mutex> lk(c.mu);
   DevCache &d = c.dev[device];
-  if (!d.limit) d.limit = cache_limit();
+  if (!d.limit_set) {
+    d.limit = cache_limit();
+    d.limit_set = true;
+  }
   // best fit among blocks of at most 1/8 more than requested
   const size_t slack = sz / 8;
   auto take = [&](void) -> void * {
