@@ -36,6 +36,7 @@ enum ForkAt { FORK_START = 0, FORK_AFTER_P2M = 1, FORK_AFTER_M2M = 2 };
 // M2L work tiles: 4 waves x RT row tiles of 16 pairs
 constexpr int M2L_RT32 = 4, M2L_RT64 = 2;
 constexpr int M2L_ROWS32 = 4 * M2L_RT32 * 16, M2L_ROWS64 = 4 * M2L_RT64 * 16;
+constexpr int LEVEL_RT = 1, LEVEL_ROWS = 4 * LEVEL_RT * 16;  // per-level M2M and L2L tiles
 constexpr double PI = 3.14159265358979323846;
 constexpr double K_COULOMB = 332.06;
 
@@ -207,11 +208,13 @@ struct Tree {
   // level's cells grouped by octant (the operators depend on the octant
   // only); src = parent cell (L2L input), self = the cell (M2M input), both
   // global indices; dest = cell index within the level.  Tiles of level l
-  // are [t0[l], t1[l]) (FP32) and [t0_64[l], t1_64[l]).
+  // are [t0[l], t1[l]) in both precisions.
   struct L2LList {
     DBuf<int32_t> src, self, dest, group_off, group_end;
-    DBuf<int32_t> tile_group, tile_row, tile_group64, tile_row64;
-    std::vector<int64_t> t0, t1, t0_64, t1_64;
+    // tiles of 64 rows (4 waves x one row tile of 16): the per-level products
+    // are small, so short tiles give more workgroups and shorter MFMA chains
+    DBuf<int32_t> tile_group, tile_row;
+    std::vector<int64_t> t0, t1;
     int64_t max_cells = 0;
   } l2lw;
 

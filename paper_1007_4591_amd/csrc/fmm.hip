@@ -1366,18 +1366,18 @@ static void level_product(Tree &T, int l, const int32_t *src, const void *table,
                           hipStream_t s) {
   const bool f64 = std::is_same<R, double>::value;
   const Tree::L2LList &LW = T.l2lw;
-  const int64_t t0 = f64 ? LW.t0_64[l] : LW.t0[l], t1 = f64 ? LW.t1_64[l] : LW.t1[l];
+  const int64_t t0 = LW.t0[l], t1 = LW.t1[l];
   if (t1 <= t0) return;
   const dim3 grid((unsigned)(t1 - t0));
 #define LEVEL_CASE(nt)                                                                                          \
   case nt:                                                                                                      \
     if (f64)                                                                                                    \
-      k_m2l<double, nt, M2L_RT64, false, USE><<<grid, 256, 0, s>>>(                                             \
-          LW.tile_group64.p + t0, LW.tile_row64.p + t0, LW.group_off.p, LW.group_end.p, src, LW.dest.p,         \
+      k_m2l<double, nt, LEVEL_RT, false, USE><<<grid, 256, 0, s>>>(                                             \
+          LW.tile_group.p + t0, LW.tile_row.p + t0, LW.group_off.p, LW.group_end.p, src, LW.dest.p,             \
           reinterpret_cast<const double *>(table), reinterpret_cast<const double *>(in),                        \
           reinterpret_cast<double *>(out));                                                                     \
     else                                                                                                        \
-      k_m2l<float, nt, M2L_RT32, true, USE><<<grid, 256, 0, s>>>(                                               \
+      k_m2l<float, nt, LEVEL_RT, true, USE><<<grid, 256, 0, s>>>(                                               \
           LW.tile_group.p + t0, LW.tile_row.p + t0, LW.group_off.p, LW.group_end.p, src, LW.dest.p,             \
           reinterpret_cast<const float *>(table), reinterpret_cast<const float *>(in),                          \
           reinterpret_cast<float *>(out));                                                                      \

@@ -714,8 +714,6 @@ static void build_l2l_lists(Tree &T, hipStream_t s) {
   const int L = T.L;
   W.t0.assign(L + 2, 0);
   W.t1.assign(L + 2, 0);
-  W.t0_64.assign(L + 2, 0);
-  W.t1_64.assign(L + 2, 0);
   W.max_cells = 0;
   if (L < 3) return;
   std::vector<uint32_t> key(T.ncell_tot);
@@ -723,10 +721,9 @@ static void build_l2l_lists(Tree &T, hipStream_t s) {
   HIP_OK(hipMemcpyAsync(key.data(), T.ckey.p, T.ncell_tot * 4, hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(par.data(), T.cparent.p, T.ncell_tot * 4, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  std::vector<int32_t> src, self, dest, goff, gend, tg, tr, tg64, tr64;
+  std::vector<int32_t> src, self, dest, goff, gend, tg, tr;
   for (int l = 3; l <= L; ++l) {
     W.t0[l] = (int64_t)tg.size();
-    W.t0_64[l] = (int64_t)tg64.size();
     const int64_t c0 = T.coff[l], c1 = c0 + T.ncell[l];
     for (uint32_t o = 0; o < 8; ++o) {
       const int32_t b = (int32_t)src.size();
@@ -741,17 +738,12 @@ static void build_l2l_lists(Tree &T, hipStream_t s) {
       const int32_t g = (int32_t)goff.size();
       goff.push_back((int32_t)o);
       gend.push_back(e);
-      for (int32_t r = b; r < e; r += M2L_ROWS32) {
+      for (int32_t r = b; r < e; r += LEVEL_ROWS) {
         tg.push_back(g);
         tr.push_back(r);
       }
-      for (int32_t r = b; r < e; r += M2L_ROWS64) {
-        tg64.push_back(g);
-        tr64.push_back(r);
-      }
     }
     W.t1[l] = (int64_t)tg.size();
-    W.t1_64[l] = (int64_t)tg64.size();
     W.max_cells = std::max<int64_t>(W.max_cells, T.ncell[l]);
   }
   auto up = [&](DBuf<int32_t> &d, const std::vector<int32_t> &h) {
@@ -765,8 +757,6 @@ static void build_l2l_lists(Tree &T, hipStream_t s) {
   up(W.group_end, gend);
   up(W.tile_group, tg);
   up(W.tile_row, tr);
-  up(W.tile_group64, tg64);
-  up(W.tile_row64, tr64);
   HIP_OK(hipStreamSynchronize(s));  // host vectors go out of scope
 }
 
