@@ -725,15 +725,27 @@ static void build_l2l_lists(Tree &T, hipStream_t s) {
   for (int l = 3; l <= L; ++l) {
     W.t0[l] = (int64_t)tg.size();
     const int64_t c0 = T.coff[l], c1 = c0 + T.ncell[l];
+    // the level's cells bucketed by octant, each bucket in cell order
+    int64_t cnt[9] = {0};
+    for (int64_t c = c0; c < c1; ++c) ++cnt[(key[c] & 7u) + 1];
+    for (int o = 0; o < 8; ++o) cnt[o + 1] += cnt[o];
+    const size_t base = src.size();
+    src.resize(base + (c1 - c0));
+    self.resize(base + (c1 - c0));
+    dest.resize(base + (c1 - c0));
+    {
+      int64_t at[8];
+      for (int o = 0; o < 8; ++o) at[o] = cnt[o];
+      for (int64_t c = c0; c < c1; ++c) {
+        const size_t k = base + at[key[c] & 7u]++;
+        src[k] = par[c];
+        self[k] = (int32_t)c;
+        dest[k] = (int32_t)(c - c0);
+      }
+    }
     for (uint32_t o = 0; o < 8; ++o) {
-      const int32_t b = (int32_t)src.size();
-      for (int64_t c = c0; c < c1; ++c)
-        if ((key[c] & 7u) == o) {
-          src.push_back(par[c]);
-          self.push_back((int32_t)c);
-          dest.push_back((int32_t)(c - c0));
-        }
-      const int32_t e = (int32_t)src.size();
+      const int32_t b = (int32_t)(base + cnt[o]);
+      const int32_t e = (int32_t)(base + cnt[o + 1]);
       if (e == b) continue;
       const int32_t g = (int32_t)goff.size();
       goff.push_back((int32_t)o);
