@@ -106,6 +106,29 @@ inline int pad16(int v) { return (v + 15) / 16 * 16; }
 __host__ __device__ inline int idx_re(int n, int m) { return m == 0 ? n * n : n * n + 2 * m - 1; }
 __host__ __device__ inline int idx_im(int n, int m) { return n * n + 2 * m; }
 
+// Storage order of every expansion row (multipole, local, and the rows of
+// the M2L, M2M and L2L products).  A row of ps = pad16(p^2) reals is four
+// blocks of ps/4; coefficient k (the packed index above) goes to place
+// k mod r4 of block k div r4, with r4 = ceil(p^2/4), and the rest of each
+// block is zero.  The MFMA products take one block per lane group along K,
+// so the k-steps from r4 on would multiply zeros only and are skipped.
+__host__ __device__ inline int coef_r4(int p) { return (p * p + 3) / 4; }
+__host__ __device__ inline int coef_pos(int k, int p, int ps) {
+  const int r4 = coef_r4(p);
+  return (k / r4) * (ps / 4) + k % r4;
+}
+// inverse of coef_pos: the coefficient stored at place i, or -1 (padding)
+__host__ __device__ inline int coef_at(int i, int p, int ps) {
+  const int r4 = coef_r4(p), b = i / (ps / 4), o = i - b * (ps / 4);
+  const int k = b * r4 + o;
+  return (o < r4 && k < p * p) ? k : -1;
+}
+// k-steps of an MFMA product over rows of NT column tiles: the largest r4 of
+// the orders whose rows have NT tiles (pad16(p^2) = 16 NT)
+constexpr int kk_used(int NT) {
+  return NT == 1 ? 4 : NT == 2 ? 7 : NT == 3 ? 9 : NT == 4 ? 16 : NT == 6 ? 21 : NT == 7 ? 25 : NT == 8 ? 31 : NT * 4;
+}
+
 // ---------------------------------------------------------------- tables
 
 // FP64 translation operators for order p and a MAC (host-built, cached).

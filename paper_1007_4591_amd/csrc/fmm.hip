@@ -258,10 +258,12 @@ __global__ void __launch_bounds__(64) k_p2m(int p, int ps, int64_t C, const int4
   }
   __syncthreads();
   R *out = M + c * ps;
-  for (int k = lane; k < ps; k += 64) {
+  for (int i = lane; i < ps; i += 64) {
+    const int k = coef_at(i, p, ps);
     R acc = R(0);
-    for (int l = 0; l < 64; ++l) acc += row[l * stride + k];
-    out[k] = acc;
+    if (k >= 0)
+      for (int l = 0; l < 64; ++l) acc += row[l * stride + k];
+    out[i] = acc;
   }
 }
 
@@ -322,11 +324,12 @@ __global__ void __launch_bounds__(64) k_p2m_fixed(int ps, int64_t C, const int4 
   for (int k = 0; k < NC; ++k) part[lane][k] = acc[k];
   __syncthreads();
   R *out = M + c * ps;
-  for (int k = lane; k < ps; k += 64) {
+  for (int i = lane; i < ps; i += 64) {
+    const int k = coef_at(i, P, ps);
     R t = R(0);
-    if (k < NC)
+    if (k >= 0)
       for (int l = 0; l < 64; ++l) t += part[l][k];
-    out[k] = t;
+    out[i] = t;
   }
 }
 
@@ -460,7 +463,7 @@ k_m2l(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ tile_r
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = Acc{0, 0, 0, 0};
 #pragma unroll
-  for (int kk = 0; kk < KK; ++kk) {
+  for (int kk = 0; kk < kk_used(NT); ++kk) {
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) {
       const R b = B[(kk * NT + ct) * 64];
@@ -553,7 +556,7 @@ __device__ __forceinline__ void m2l_tiles(const int32_t *__restrict__ tile_group
       for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
     const float *B = reinterpret_cast<const float *>(Bsrc) + lane;
 #pragma unroll
-    for (int kk = 0; kk < KK; ++kk) {
+    for (int kk = 0; kk < kk_used(NT); ++kk) {
 #pragma unroll
       for (int ct = 0; ct < NT; ++ct) {
         const float b = B[(kk * NT + ct) * 64];
@@ -687,7 +690,7 @@ k_m2l_pers64(const int32_t *__restrict__ tile_group, const int32_t *__restrict__
       for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
     const double *B = reinterpret_cast<const double *>(Bs) + lane;
 #pragma unroll
-    for (int kk = 0; kk < KK; ++kk) {
+    for (int kk = 0; kk < kk_used(NT); ++kk) {
 #pragma unroll
       for (int ct = 0; ct < NT; ++ct) {
         const double b = B[(kk * NT + ct) * 64];
@@ -811,14 +814,14 @@ __global__ void __launch_bounds__(256) k_downward(int p, int ps, int64_t c0, int
   __syncthreads();
   auto Lre = [&](int n, int m) -> R {  // Re L_n^m for any m
     if (n >= p || m > n || -m > n) return R(0);
-    if (m >= 0) return Ls[idx_re(n, m)];
-    return ((-m) & 1) ? -Ls[idx_re(n, -m)] : Ls[idx_re(n, -m)];
+    if (m >= 0) return Ls[coef_pos(idx_re(n, m), p, ps)];
+    return ((-m) & 1) ? -Ls[coef_pos(idx_re(n, -m), p, ps)] : Ls[coef_pos(idx_re(n, -m), p, ps)];
   };
   auto Lim = [&](int n, int m) -> R {
     if (n >= p || m > n || -m > n || m == 0) return R(0);
-    if (m > 0) return Ls[idx_im(n, m)];
+    if (m > 0) return Ls[coef_pos(idx_im(n, m), p, ps)];
     // L^{-m} = (-1)^m conj(L^m)
-    return ((-m) & 1) ? Ls[idx_im(n, -m)] : -Ls[idx_im(n, -m)];
+    return ((-m) & 1) ? Ls[coef_pos(idx_im(n, -m), p, ps)] : -Ls[coef_pos(idx_im(n, -m), p, ps)];
   };
   for (int k = lane; k < np2; k += nthr) {
     int n = 0;
@@ -1657,7 +1660,7 @@ void debug_expansions(Tree &T, int precision, int which, double *out_host, hipSt
     for (size_t i = 0; i < n; ++i) full[i] = f[i];
   }
   for (int64_t c = 0; c < T.ncell_tot; ++c)
-    for (int k = 0; k < np2; ++k) out_host[(size_t)c * np2 + k] = full[(size_t)c * T.ps + k];
+    for (int k = 0; k < np2; ++k) out_host[(size_t)c * np2 + k] = full[(size_t)c * T.ps + coef_pos(k, T.p, T.ps)];
 }
 
 void debug_fields(Tree &T, int precision, double *near_host, double *far_host, hipStream_t s) {

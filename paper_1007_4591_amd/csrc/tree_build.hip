@@ -789,7 +789,9 @@ void upload_tables(Tree &T, hipStream_t s) {
     const int ps = T.ps, noff = tb.noff();
     const int KK = ps / 4, NT = ps / 16;
     // MFMA-swizzled M2L: for k-step kk and column tile ct, lane l holds
-    // B[k][j] = T[out = ct*16 + l%16][in = (l/16)*KK + kk]
+    // B[k][j] = T[out][in] for the coefficients stored at places
+    // ct*16 + l%16 (out) and (l/16)*KK + kk (in), zero at padding places
+    const int p = T.p;
     std::vector<float> sw32((size_t)noff * KK * NT * 64);
     std::vector<double> sw64(sw32.size());
     for (int o = 0; o < noff; ++o) {
@@ -797,8 +799,8 @@ void upload_tables(Tree &T, hipStream_t s) {
       for (int kk = 0; kk < KK; ++kk)
         for (int ct = 0; ct < NT; ++ct)
           for (int l = 0; l < 64; ++l) {
-            int out = ct * 16 + (l % 16), in = (l / 16) * KK + kk;
-            double v = Tm[(size_t)out * ps + in];
+            const int out = coef_at(ct * 16 + (l % 16), p, ps), in = coef_at((l / 16) * KK + kk, p, ps);
+            const double v = (out >= 0 && in >= 0) ? Tm[(size_t)out * ps + in] : 0.0;
             size_t at = (((size_t)o * KK + kk) * NT + ct) * 64 + l;
             sw64[at] = v;
             sw32[at] = (float)v;
@@ -815,10 +817,11 @@ void upload_tables(Tree &T, hipStream_t s) {
       for (int kk = 0; kk < KK; ++kk)
         for (int ct = 0; ct < NT; ++ct)
           for (int l = 0; l < 64; ++l) {
-            const int out = ct * 16 + (l % 16), in = (l / 16) * KK + kk;
+            const int out = coef_at(ct * 16 + (l % 16), p, ps), in = coef_at((l / 16) * KK + kk, p, ps);
             const size_t at = (((size_t)o * KK + kk) * NT + ct) * 64 + l;
-            a[at] = tb.m2m[((size_t)o * ps + out) * ps + in];
-            b[at] = tb.l2l[((size_t)o * ps + out) * ps + in];
+            const bool real = out >= 0 && in >= 0;
+            a[at] = real ? tb.m2m[((size_t)o * ps + out) * ps + in] : 0.0;
+            b[at] = real ? tb.l2l[((size_t)o * ps + out) * ps + in] : 0.0;
           }
     std::vector<float> a32(a.size()), b32(b.size());
     for (size_t i = 0; i < a.size(); ++i) a32[i] = (float)a[i];
