@@ -36,6 +36,9 @@ enum ForkAt { FORK_START = 0, FORK_AFTER_P2M = 1, FORK_AFTER_M2M = 2 };
 // M2L work tiles: 4 waves x RT row tiles of 16 pairs
 constexpr int M2L_RT32 = 4, M2L_RT64 = 2;
 constexpr int M2L_ROWS32 = 4 * M2L_RT32 * 16, M2L_ROWS64 = 4 * M2L_RT64 * 16;
+// row tiles per wave of the persistent FP32 M2L (a tile list tile is split into
+// units of 4 * M2L_PERS_RT * 16 rows)
+constexpr int M2L_PERS_RT = 2;
 constexpr int LEVEL_RT = 1, LEVEL_ROWS = 4 * LEVEL_RT * 16;  // per-level M2M and L2L tiles
 constexpr double PI = 3.14159265358979323846;
 constexpr double K_COULOMB = 332.06;

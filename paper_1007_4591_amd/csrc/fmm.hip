@@ -490,15 +490,23 @@ k_m2l(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ tile_r
 }
 
 // Persistent FP32 M2L.  A workgroup (4 waves, one per SIMD) walks a
-// contiguous range of tiles; the ranges are XCD-aware, so the ranges of one
-// XCD are adjacent and consecutive tiles mostly share their offset group.
-// The operator is reloaded into LDS only when the offset group changes
-// (about once per nine tiles, instead of once per tile).  Two workgroups
-// share a CU and drift out of step, so one's loads overlap the other's MFMA
-// work; one tile per workgroup kept the two in lock step (gather, then
-// products, then stores at the same time) and overlapped little.  The
-// arithmetic per tile is that of k_m2l (same operand layouts, same K order),
-// so results are identical.
+// contiguous range of work units; the ranges are XCD-aware, so the ranges of
+// one XCD are adjacent and consecutive units mostly share their offset group.
+// A unit is one part of a tile of the tile list (M2L_ROWS32 rows): 4 waves x
+// RT x 16 rows.  The operator is reloaded into LDS only when the offset group
+// changes.  Two workgroups share a CU and drift out of step, so one's loads
+// overlap the other's MFMA work.
+// Per unit, the source rows of the next unit are requested right after the
+// products and before this unit's results are stored: the vector memory
+// counter retires in order, so a wait for loads issued after the stores
+// would also wait for the stores.  The results go out through a per-wave LDS
+// staging area, 16 rows at a time, so that each lane stores 16 contiguous
+// bytes of a row (RT x PS / 4 stores per wave and unit instead of RT x 4 x
+// NT): with fewer than 64 memory operations behind it, the wait for the
+// prefetched rows is not capped by the counter's range.  RT = 2 keeps the
+// accumulators, the prefetched rows and the staging within 256 registers.
+// The arithmetic per row is that of k_m2l (same operand layouts, same K
+// order), so results are identical.
 template <int NT, int RT>
 __device__ __forceinline__ void m2l_tiles(const int32_t *__restrict__ tile_group,
                                           const int32_t *__restrict__ tile_row,
@@ -506,28 +514,37 @@ __device__ __forceinline__ void m2l_tiles(const int32_t *__restrict__ tile_group
                                           const int32_t *__restrict__ group_end,
                                           const int32_t *__restrict__ src, const int32_t *__restrict__ dest,
                                           const float *__restrict__ Tsw, const float *__restrict__ M,
-                                          float *__restrict__ out, int ntiles, float4 *Bs) {
+                                          float *__restrict__ out, int ntiles, float4 *Bs, float *Ts) {
   constexpr int PS = NT * 16;
   constexpr int KK = PS / 4;
   constexpr int TB4 = KK * NT * 16;          // float4 per operator
+  constexpr int UROWS = 4 * RT * 16;         // rows per unit
+  static_assert(M2L_ROWS32 % UROWS == 0, "a tile splits into whole units");
+  constexpr int SUB = M2L_ROWS32 / UROWS;    // units per tile
+  constexpr int TS = PS + 4;                 // staging row stride (floats, 16-byte aligned)
+  constexpr int F4 = PS / 4;                 // float4 per result row
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i16 = lane & 15, kq = lane >> 4;
   const int nwg = gridDim.x;
   const int wg = xcd_block(blockIdx.x, nwg);
-  const int t0 = (int)((int64_t)ntiles * wg / nwg), t1 = (int)((int64_t)ntiles * (wg + 1) / nwg);
-  if (t0 >= t1) return;  // uniform over the workgroup
+  const int64_t nunits = (int64_t)ntiles * SUB;
+  const int u0 = (int)(nunits * wg / nwg), u1 = (int)(nunits * (wg + 1) / nwg);
+  if (u0 >= u1) return;  // uniform over the workgroup
+  float *Tw = Ts + wave * 16 * TS;
 
-  struct TileIn {
+  struct UnitIn {
     int g, end, row0;
   };
-  auto tile_in = [&](int t) {
-    TileIn s;
+  auto unit_in = [&](int u) {
+    UnitIn s;
+    const int t = u / SUB;
     s.g = tile_group[t];
     s.end = group_end[s.g];
-    s.row0 = tile_row[t] + wave * (16 * RT);
+    s.row0 = tile_row[t] + (u - t * SUB) * UROWS + wave * (16 * RT);
     return s;
   };
-  auto load_a = [&](const TileIn &s, float (&a)[RT][KK], int (&d)[RT][4]) {
+  // lane (i16, kq) supplies row i16 of a row tile, inputs kq*KK .. kq*KK+KK-1
+  auto load_rows = [&](const UnitIn &s, float (&a)[RT][KK]) {
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       const int sr = src[min(s.row0 + rt * 16 + i16, s.end - 1)];
@@ -540,63 +557,86 @@ __device__ __forceinline__ void m2l_tiles(const int32_t *__restrict__ tile_group
         a[rt][4 * v + 2] = q.z;
         a[rt][4 * v + 3] = q.w;
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int rr = min(s.row0 + rt * 16 + 4 * kq + q, s.end - 1);
-        d[rt][q] = dest[rr];
-      }
     }
   };
-  auto products = [&](const TileIn &s, const float (&a)[RT][KK], const int (&d)[RT][4], const float4 *Bsrc) {
-    if (s.row0 >= s.end) return;
-    f32x4 acc[RT][NT];
+  // lane (i16, .) holds the destination of row i16 of each row tile
+  auto load_dest = [&](const UnitIn &s, int (&d)[RT]) {
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const float *B = reinterpret_cast<const float *>(Bsrc) + lane;
-#pragma unroll
-    for (int kk = 0; kk < kk_used(NT); ++kk) {
-#pragma unroll
-      for (int ct = 0; ct < NT; ++ct) {
-        const float b = B[(kk * NT + ct) * 64];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][kk], b, acc[rt][ct], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (s.row0 + rt * 16 + 4 * kq + q < s.end) {
-          float *o = out + (size_t)d[rt][q] * PS + i16;
-#pragma unroll
-          for (int ct = 0; ct < NT; ++ct) o[ct * 16] = acc[rt][ct][q];
-        }
+    for (int rt = 0; rt < RT; ++rt) d[rt] = dest[min(s.row0 + rt * 16 + i16, s.end - 1)];
   };
-  auto stage_b = [&](int g, float4 *dst) {
+  auto stage_b = [&](int g) {
     const float4 *Bg = reinterpret_cast<const float4 *>(Tsw) + (size_t)group_off[g] * TB4;
-    for (int v = threadIdx.x; v < TB4; v += 256) dst[v] = Bg[v];
+    for (int v = threadIdx.x; v < TB4; v += 256) Bs[v] = Bg[v];
   };
 
   float a[RT][KK];
-  int d[RT][4];
-  TileIn cur = tile_in(t0);
-  stage_b(cur.g, Bs);
+  int d[RT];
+  UnitIn cur = unit_in(u0);
+  stage_b(cur.g);
+  load_rows(cur, a);
+  load_dest(cur, d);
   __syncthreads();
-  for (int t = t0; t < t1; ++t) {
-    if (t > t0) {
-      const TileIn nxt = tile_in(t);
+  for (int u = u0; u < u1; ++u) {
+    const bool work = cur.row0 < cur.end;  // uniform over the wave
+    f32x4 acc[RT][NT];
+    if (work) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+      const float *B = reinterpret_cast<const float *>(Bs) + lane;
+#pragma unroll
+      for (int kk = 0; kk < kk_used(NT); ++kk) {
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+          const float b = B[(kk * NT + ct) * 64];
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt)
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][kk], b, acc[rt][ct], 0, 0, 0);
+        }
+      }
+    }
+    const bool more = u + 1 < u1;
+    UnitIn nxt = cur;
+    int dn[RT];
+    if (more) {
+      nxt = unit_in(u + 1);
+      load_rows(nxt, a);
+      load_dest(nxt, dn);
+    }
+    __asm__ volatile("" ::: "memory");  // keep the prefetch ahead of the stores
+    if (work) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        // MFMA output: register q of lane (i16, kq) is row 4 kq + q, column
+        // ct * 16 + i16 of column tile ct
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct) Tw[(4 * kq + q) * TS + ct * 16 + i16] = acc[rt][ct][q];
+        __builtin_amdgcn_wave_barrier();
+        // 16 rows x F4 float4, 64 lanes at a time (16 F4 = 64 NT: whole passes)
+#pragma unroll
+        for (int v = 0; v < NT; ++v) {
+          const int f = lane + 64 * v;
+          const int row = f / F4, c4 = f - row * F4;
+          const int dr = __shfl(d[rt], row);
+          const float4 val = *reinterpret_cast<const float4 *>(Tw + row * TS + 4 * c4);
+          if (cur.row0 + rt * 16 + row < cur.end) *reinterpret_cast<float4 *>(out + (size_t)dr * PS + 4 * c4) = val;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    if (more) {
       if (group_off[nxt.g] != group_off[cur.g]) {
         __syncthreads();  // every wave is done with the current operator
-        stage_b(nxt.g, Bs);
+        stage_b(nxt.g);
         __syncthreads();
       }
       cur = nxt;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) d[rt] = dn[rt];
     }
-    load_a(cur, a, d);
-    products(cur, a, d, Bs);
   }
 }
 
@@ -607,7 +647,8 @@ k_m2l_pers(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ t
            const int32_t *__restrict__ src, const int32_t *__restrict__ dest, const float *__restrict__ Tsw,
            const float *__restrict__ M, float *__restrict__ out, int ntiles) {
   __shared__ float4 Bs[NT * 4 * NT * 16];
-  m2l_tiles<NT, RT>(tile_group, tile_row, group_off, group_end, src, dest, Tsw, M, out, ntiles, Bs);
+  __shared__ float Ts[4 * 16 * (NT * 16 + 4)];
+  m2l_tiles<NT, RT>(tile_group, tile_row, group_off, group_end, src, dest, Tsw, M, out, ntiles, Bs, Ts);
 }
 
 // Persistent FP64 M2L, for large pair counts (on small ones one tile per
@@ -1538,7 +1579,8 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
           ML.tile_group64.p, ML.tile_row64.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p, T.t_m2l64,             \
           reinterpret_cast<const double *>(M), reinterpret_cast<double *>(m2l));                               \
     else if (T.m2l_persistent)                                                                                  \
-      k_m2l_pers<nt, M2L_RT32><<<dim3((unsigned)std::min<int64_t>(ML.ntiles, 2 * T.n_cu)), 256, 0, s>>>(      \
+      k_m2l_pers<nt, M2L_PERS_RT><<<dim3((unsigned)std::min<int64_t>(ML.ntiles * (M2L_ROWS32 / (64 * M2L_PERS_RT)), \
+                                                                   2 * T.n_cu)), 256, 0, s>>>(                 \
           ML.tile_group.p, ML.tile_row.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p, T.t_m2l32,      \
           reinterpret_cast<const float *>(M), reinterpret_cast<float *>(m2l), (int)ML.ntiles);                 \
     else                                                                                                       \
