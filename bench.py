@@ -185,9 +185,9 @@ def main():
                 "avg_ms": p2p_ms, "launches": live["p2p"][1], "traffic": pmc_traffic("k_p2p_near<float, 0, 0, 1>")}
     roof_p2p["frac"] = roof_p2p["achieved"] / roof_p2p["peak"]
     roof_p2p["frac_of_packed_peak"] = roof_p2p["achieved"] / (PEAK_FP32_PACKED / 1e12)
-    roof_m2l = {"bound": "mfma", "kernel": "k_m2l_pers<7,4> (M2L, FP32 MFMA, persistent)",
+    roof_m2l = {"bound": "mfma", "kernel": "k_m2l_pers<7,2> (M2L, FP32 MFMA, persistent)",
                 "achieved": m2l_flops / (m2l_ms / 1e3) / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                "avg_ms": m2l_ms, "launches": live["m2l"][1], "traffic": pmc_traffic("k_m2l_pers<7, 4>")}
+                "avg_ms": m2l_ms, "launches": live["m2l"][1], "traffic": pmc_traffic("k_m2l_pers<7, 2>")}
     roof_m2l["frac"] = roof_m2l["achieved"] / roof_m2l["peak"]
     # the same kernels alone on the chip (near field not concurrent): a
     # second tree built with the concurrent near field switched off
