@@ -86,31 +86,42 @@ def test_ragged_panel_counts(keep, ncrit):
 
 def test_expansion_orders():
     """p = 1 (monopole only) to the maximum p = 11: every order runs, the FMM
-    error falls with p, and p >= 10 meets the 1e-5 matvec bar."""
+    error falls with p, and p >= 10 meets the 1e-5 matvec bar.  FP32 runs
+    every operator at every order too (the kernels for orders other than
+    10, and 8 column tiles at p = 11): its error is the FP64 one plus FP32
+    rounding."""
     B = lib()
     p = synth.blobby(5)
-    errs = {}
+    errs, errs32 = {}, {}
     for order in (1, 4, 8, 10, 11):
-        t, e = _ops_vs_dense(B, p.verts, p.tris, p.charge_pos[:50], B.Params(p=order, ncrit=32), precs=(0,))
+        t, e = _ops_vs_dense(B, p.verts, p.tris, p.charge_pos[:50], B.Params(p=order, ncrit=32))
         errs[order] = e[(0, 0)]
+        errs32[order] = {op: (e[(op, 1)], e[(op, 0)]) for op in range(6)}
         B.tree_destroy(t)
     print(f"[edges] orders {errs}", flush=True)
+    print(f"[edges] orders fp32 (fp32, fp64) {errs32}", flush=True)
     assert errs[1] > errs[4] > errs[8] > errs[10] >= 0.5 * errs[11]
     assert errs[10] <= 1e-5 and errs[11] <= 1e-5
+    for order, per_op in errs32.items():
+        for op, (e32, e64) in per_op.items():
+            assert e32 <= e64 + 2e-6, (order, op, e32, e64)
 
 
 def test_theta_extremes():
     """The smallest and largest accepted theta (0.3: a large near stencil and
     operator table; 1.0: few near leaves, loosely separated far pairs)
-    against theta = 0.5: the error grows with theta."""
+    against theta = 0.5: the error grows with theta.  FP32 at each theta:
+    the FP64 error plus FP32 rounding."""
     B = lib()
     p = synth.kirkwood(4, n_charges=20)
-    errs, noff = {}, {}
+    errs, noff, gap32 = {}, {}, {}
     for theta in (0.3, 0.5, 1.0):
-        t, e = _ops_vs_dense(B, p.verts, p.tris, p.charge_pos, B.Params(theta=theta, ncrit=16), precs=(0,))
-        errs[theta] = max(e.values())
+        t, e = _ops_vs_dense(B, p.verts, p.tris, p.charge_pos, B.Params(theta=theta, ncrit=16))
+        errs[theta] = max(v for (op, pr), v in e.items() if pr == 0)
+        gap32[theta] = max(e[(op, 1)] - e[(op, 0)] for op in range(6))
         noff[theta] = t.info["n_offsets"]
         B.tree_destroy(t)
-    print(f"[edges] theta errors {errs} offsets {noff}", flush=True)
+    print(f"[edges] theta errors {errs} offsets {noff} fp32 excess {gap32}", flush=True)
     assert errs[0.3] < errs[0.5] < errs[1.0]
     assert errs[0.3] <= 1e-7 and errs[0.5] <= 1e-5 and errs[1.0] <= 5e-2
+    assert max(gap32.values()) <= 2e-6
