@@ -641,7 +641,7 @@ __device__ __forceinline__ void m2l_tiles(const int32_t *__restrict__ tile_group
 }
 
 template <int NT, int RT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 7 ? 2 : 1)))
 k_m2l_pers(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ tile_row,
            const int32_t *__restrict__ group_off, const int32_t *__restrict__ group_end,
            const int32_t *__restrict__ src, const int32_t *__restrict__ dest, const float *__restrict__ Tsw,
