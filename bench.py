@@ -70,8 +70,8 @@ def pmc_traffic(kernel):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="blobby")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=4096)
@@ -130,14 +130,19 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     last = None
+    each = []
     for _ in range(args.steps):
+        ts = time.perf_counter()
         last = step(record=True)
+        torch.cuda.synchronize()  # a step ends in host reads already; this only closes its interval
+        each.append(1000.0 * (time.perf_counter() - ts))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = 1000.0 * dt / args.steps
     tree, x, sinfo, ainfo, dG, bib = last
-    print(f"[bench] step {ms_per_step:.2f} ms dG={dG:.6f} bibee={bib:.6f} solve iters={sinfo.iters} "
-          f"outer={sinfo.outer_iters} adjoint iters={ainfo.iters}", file=sys.stderr, flush=True)
+    print(f"[bench] step {ms_per_step:.2f} ms (each: {', '.join(f'{v:.1f}' for v in each)}) dG={dG:.6f} "
+          f"bibee={bib:.6f} solve iters={sinfo.iters} outer={sinfo.outer_iters} adjoint iters={ainfo.iters}",
+          file=sys.stderr, flush=True)
 
     # ---- a plain copy of known size (reference for FETCH_SIZE / WRITE_SIZE)
     if args.calib_copy_mb > 0:
@@ -247,7 +252,8 @@ def main():
 
     out = {
         "metric": METRIC, "value": N / (ms_per_step / 1e3), "unit": "panels/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "ms_each_step": [round(v, 2) for v in each], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{prob.name}: {N} panels, {Q} charges, eps 4/80, p=10, theta=0.5, ncrit=64; "
                                "step = tree build + FP32-refined solve to 1e-6 + energy + BIBEE + adjoint",
