@@ -133,6 +133,9 @@ def main():
     each = []
     for _ in range(args.steps):
         ts = time.perf_counter()
+        # the previous step's tree is destroyed before the next is built, as
+        # in the warm-up steps, so its device blocks return to the cache
+        last = None
         last = step(record=True)
         torch.cuda.synchronize()  # a step ends in host reads already; this only closes its interval
         each.append(1000.0 * (time.perf_counter() - ts))
