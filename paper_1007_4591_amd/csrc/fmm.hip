@@ -497,16 +497,14 @@ k_m2l(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ tile_r
 // changes.  Two workgroups share a CU and drift out of step, so one's loads
 // overlap the other's MFMA work.
 // Per unit, the source rows of the next unit are requested right after the
-// products and before this unit's results are stored: the vector memory
-// counter retires in order, so a wait for loads issued after the stores
-// would also wait for the stores.  The results go out through a per-wave LDS
-// staging area, 16 rows at a time, so that each lane stores 16 contiguous
-// bytes of a row (RT x PS / 4 stores per wave and unit instead of RT x 4 x
-// NT): with fewer than 64 memory operations behind it, the wait for the
-// prefetched rows is not capped by the counter's range.  RT = 2 keeps the
-// accumulators, the prefetched rows and the staging within 256 registers.
-// The arithmetic per row is that of k_m2l (same operand layouts, same K
-// order), so results are identical.
+// products and before this unit's results are stored, so the latency of the
+// gather runs alongside that of the stores instead of after it.  The results
+// go out through a per-wave LDS staging area, 16 rows at a time, so that each
+// lane stores 16 contiguous bytes of a row (RT x PS / 4 stores per wave and
+// unit instead of RT x 4 x NT).  RT = 2 keeps the accumulators, the
+// prefetched rows and the staging within 256 registers.  The arithmetic per
+// row is that of k_m2l (same operand layouts, same K order), so results are
+// identical.
 template <int NT, int RT>
 __device__ __forceinline__ void m2l_tiles(const int32_t *__restrict__ tile_group,
                                           const int32_t *__restrict__ tile_row,
