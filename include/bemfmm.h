@@ -12,8 +12,12 @@
  *     K'_ij = a_j n_i . grad G(c_i, c_j), K'_ii = 0,  G = 1/(4 pi |r - r'|),
  *     phi = C x,  (C x)_q = sum_j a_j x_j G(r_q, c_j),
  *     dG = (2 pi K / eps_in) q^T C x,  K = 332.06 kcal A / (mol e^2).
- *   Section 2.2 (BIBEE, eq. CFA): BIBEE/CFA takes x = f E, BIBEE/P takes
- *     x = f E / (1 - f/2); the energy is then computed as above.
+ *   Section 2.2 (BIBEE, eq. CFA and the scale factors 0 and +1/2 named
+ *     after it): the principal-value operator K' is replaced by -1/2, 0 or
+ *     +1/2 times the identity, which gives x = f E (CFA), f E / (1 - f/2)
+ *     (P) or f E / (1 - f); the energy is then computed as above.
+ *   Section 4.4 (eq. binding-free-energy-estimate): the binding energy is
+ *     the solvation energy of the complex minus those of its two parts.
  *   Section 2.3 (FMM): every product with K', B, C and their transposes is
  *     a fast-multipole sum over an octree (P2M, M2M, M2L, L2L, L2P, P2P).
  *
@@ -88,7 +92,18 @@ typedef enum {
   BEMFMM_OP_CT = 5  /* y[N] = C^T x,                           x[Q]   */
 } bemfmm_op;
 
-typedef enum { BEMFMM_BIBEE_CFA = 0, BEMFMM_BIBEE_P = 1 } bemfmm_bibee;
+/* BIBEE surface charge x = s f E: the principal-value operator K' replaced
+ * by -1/2 (CFA, s = 1), 0 (P, s = 1/(1 - f/2)) or +1/2 (s = 1/(1 - f)). */
+typedef enum { BEMFMM_BIBEE_CFA = 0, BEMFMM_BIBEE_P = 1, BEMFMM_BIBEE_PLUS_HALF = 2 } bemfmm_bibee;
+
+/* How bemfmm_binding_energy computes each solvation energy: the full BEM
+ * solve (bemfmm_solve_bem + bemfmm_solvation_energy) or one BIBEE variant. */
+typedef enum {
+  BEMFMM_ENERGY_BEM = 0,
+  BEMFMM_ENERGY_BIBEE_CFA = 1,
+  BEMFMM_ENERGY_BIBEE_P = 2,
+  BEMFMM_ENERGY_BIBEE_PLUS_HALF = 3
+} bemfmm_energy_method;
 
 /* Multipole acceptance between two same-level cells whose integer offset
  * (in cell widths) is o:
@@ -149,7 +164,9 @@ int bemfmm_build_tree(const double *verts, int64_t nv, const int32_t *tris, int6
 /* Move the charges (charge_pos [nq*3], same count and order) without
  * rebuilding: every charge keeps its leaf cell, so the FMM operator changes
  * continuously (finite differences on a frozen tree).  EINVAL if a charge
- * leaves its leaf box by more than a quarter of the leaf side. */
+ * leaves its leaf box by more than 1/1000 of the leaf side (beyond that the
+ * near/far lists, built for charges inside their leaves, would no longer
+ * guarantee the MAC's separation); the charges are then left unchanged. */
 int bemfmm_set_charges(bemfmm_tree *tree, const double *charge_pos, void *stream);
 
 int bemfmm_tree_destroy(bemfmm_tree *tree);
@@ -171,9 +188,10 @@ int bemfmm_fmm_matvec(bemfmm_tree *tree, int op, int precision, const double *x,
 int bemfmm_solve_bem(bemfmm_tree *tree, const double *q, double *x, double tol, int maxit,
                      int restart, int precision, bemfmm_solve_info *info_host, void *stream);
 
-/* BIBEE energy (Section 2.2, eq. CFA and its scale-factor-0 variant):
- * x = f E (CFA) or f E / (1 - f/2) (P), then dG = (2 pi K/eps_in) q^T C x,
- * written to *dG_host in kcal/mol.  q: [Q]. */
+/* BIBEE energy (Section 2.2, eq. CFA and its scale-factor 0 and +1/2
+ * variants): x = f E (CFA), f E / (1 - f/2) (P) or f E / (1 - f)
+ * (PLUS_HALF), then dG = (2 pi K/eps_in) q^T C x, written to *dG_host in
+ * kcal/mol.  q: [Q].  EINVAL for another kind. */
 int bemfmm_bibee_energy(bemfmm_tree *tree, const double *q, int kind, int precision,
                         double *dG_host, void *stream);
 
@@ -193,6 +211,22 @@ int bemfmm_solvation_energy(bemfmm_tree *tree, const double *q, const double *x,
 int bemfmm_adjoint_grad(bemfmm_tree *tree, const double *q, const double *x, double tol, int maxit,
                         int restart, int precision, double *dG_dq, double *dG_dpos,
                         bemfmm_solve_info *info_host, void *stream);
+
+/* Electrostatic binding energy (Section 4.4, eq.
+ * binding-free-energy-estimate): dG_bind = dG_complex - dG_protein -
+ * dG_inhibitor, each the solvation energy of its own tree (surface and
+ * charges) and charge values q_* [Q of that tree].  method is a
+ * bemfmm_energy_method: BEM solves each system to `tol` (maxit, restart
+ * and precision as for bemfmm_solve_bem; the energies' C products then run
+ * in FP64 unless precision is FP32); a BIBEE method takes that variant's
+ * surface charge at `precision` (tol, maxit and restart unused).
+ * dG_host[4] receives (bind, complex, protein, inhibitor) in kcal/mol.  The
+ * three trees must live on one device; they may be the same tree.  ENOCONV
+ * if a BEM solve did not converge (dG_host then unspecified). */
+int bemfmm_binding_energy(bemfmm_tree *complex_tree, const double *q_complex, bemfmm_tree *protein_tree,
+                          const double *q_protein, bemfmm_tree *inhibitor_tree, const double *q_inhibitor,
+                          int method, int precision, double tol, int maxit, int restart, double *dG_host,
+                          void *stream);
 
 /* Thread-local message for the last failure on this thread ("" if none). */
 const char *bemfmm_last_error(void);
@@ -238,8 +272,14 @@ int bemfmm_tree_export(const bemfmm_tree *tree, int32_t *panel_perm_host, int32_
  * per degree n: Re m=0, then Re, Im of m = 1..n. */
 int bemfmm_debug_expansions(bemfmm_tree *tree, int precision, int which, double *out_host);
 
+/* enable = 1: the products that follow also record their near (P2P) and
+ * far (L2P) parts for bemfmm_debug_fields (two extra FP64 writes per
+ * target); 0 (the default) stops recording. */
+int bemfmm_debug_record(bemfmm_tree *tree, int enable);
+
 /* Near (P2P) and far (L2P) parts of the raw field of the last
- * bemfmm_fmm_matvec at `precision`, per target in the caller's order,
+ * bemfmm_fmm_matvec at `precision` made while recording was on
+ * (bemfmm_debug_record; ESTATE otherwise), per target in the caller's order,
  * before the operator's combination (kernel 1/(4 pi |x - y|)): for panel
  * targets the normal derivative (A, B) or potential (A^T, C^T); for charge
  * targets the potential.  near_host, far_host: [n_targets]. */

@@ -18,7 +18,8 @@
  *   solve A x = f E                 (interior-limit reading of eq. ASC)
  *   (C x)_q = sum_j a_j x_j G(r_q, c_j)                               (eq. reac)
  *   dG    = (2 pi K / eps_in) q^T C x   [kcal/mol], K = 332.06 kcal A/(mol e^2)
- *   BIBEE/CFA (eq. CFA): x = f E;  BIBEE/P: x = f E / (1 - f/2).
+ *   BIBEE/CFA (eq. CFA): x = f E;  BIBEE/P: x = f E / (1 - f/2);
+ *   BIBEE with K' replaced by +1/2: x = f E / (1 - f)  (numpy front end).
  *   Adjoint: A^T y = C^T q,  d dG/dq = kappa (C x + f B^T y),
  *            d dG/dr_q = kappa q_q [grad SL(a x) + f grad DL(y)](r_q),
  *   kappa = 2 pi K / eps_in, DL(y)(r) = sum_i y_i n_i.(r - c_i)/(4 pi |r - c_i|^3).

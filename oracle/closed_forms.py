@@ -12,12 +12,16 @@ permittivity eps_out, point charges q_i at r_i with |r_i| < a.
   model for a sphere):
       dG = (K/2) sum_ij q_i q_j sum_n c_n (|r_i||r_j|)^n / a^(2n+1) P_n(cos g_ij),
       c_n = (n+1)(eps_in - eps_out) / (eps_in (n eps_in + (n+1) eps_out)).
-* BIBEE sphere series (eq. CFA and the scale-factor-0 variant of Section 2.2,
-  applied to the sphere analytically): the surface charge is f times the
-  normal field (CFA) or f/(1 - f/2) times it (P), which gives the same
-  series with
-      c_n^CFA = -f (n+1) / (eps_in (2n+1)),
-      c_n^P   = -(f / (1 - f/2)) (n+1) / (eps_in (2n+1)).
+* BIBEE sphere series (eq. CFA and the scale-factor 0 and +1/2 variants of
+  Section 2.2, applied to the sphere analytically): the surface charge is
+  s times the normal field, with s = f (CFA: the principal-value operator
+  replaced by -1/2), s = f/(1 - f/2) (P: replaced by 0) or s = f/(1 - f)
+  (replaced by +1/2).  On a sphere of radius a the normal field of a charge
+  at r' expands in Legendre terms n with weight (n+1) r'^n / a^(n+2), and the
+  single-layer potential of the n-th surface harmonic inside the sphere is
+  r^n / ((2n+1) a^(n-1)) times it, which gives the reaction-field series
+  below with
+      c_n = -s (n+1) / (eps_in (2n+1)).
   For n = 0, c_0 = c_0^CFA: the CFA is exact for a centred charge, whose
   normal field is uniform on the sphere.
 """
@@ -52,6 +56,8 @@ def _coeffs(kind: str, nmax: int, eps_in: float, eps_out: float) -> np.ndarray:
         return -f * (n + 1) / (eps_in * (2 * n + 1))
     if kind == "p":
         return -(f / (1.0 - 0.5 * f)) * (n + 1) / (eps_in * (2 * n + 1))
+    if kind == "plus_half":
+        return -(f / (1.0 - f)) * (n + 1) / (eps_in * (2 * n + 1))
     raise ValueError(kind)
 
 
@@ -74,7 +80,7 @@ def _series_matrix(pos, a, nmax, c):
 
 
 def sphere_energy(pos, q, a, eps_in, eps_out, kind="exact", nmax=60) -> float:
-    """Solvation energy of charges inside a sphere: kind in {exact, cfa, p}."""
+    """Solvation energy of charges inside a sphere: kind in {exact, cfa, p, plus_half}."""
     q = np.asarray(q, dtype=np.float64)
     M = _series_matrix(pos, a, nmax, _coeffs(kind, nmax, eps_in, eps_out))
     return 0.5 * K_COULOMB * float(q @ M @ q)

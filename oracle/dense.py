@@ -12,8 +12,13 @@ is ambiguous:
 * dG = (2 pi K / eps_in) q^T C x: eq. ASC carries no 1/eps_in on the charge
   term, so the reaction potential of the energy formula is (1/eps_in) times
   4 pi K times the single-layer potential of x.
-* BIBEE/CFA: the principal-value operator K' is replaced by -1/2 I, so
-  x = f E; BIBEE/P replaces it by 0, so x = f E / (1 - f/2).
+* BIBEE (Section 2.2, eq. CFA and the sentence after it): the
+  principal-value operator K' is replaced by a scaled identity, -1/2 I for
+  BIBEE/CFA (x = f E), 0 for BIBEE/P (x = f E / (1 - f/2)) and +1/2 I for
+  the third variant (x = f E / (1 - f)); the interior jump +1/2 of the
+  normal derivative stays in every case.
+* Binding (Section 4.4, eq. binding-free-energy-estimate): the solvation
+  energy of the complex minus those of the two unbound partners.
 """
 from __future__ import annotations
 
@@ -232,11 +237,33 @@ def bibee_x(g: Geometry, rq, q, eps_in, eps_out, kind="cfa"):
         return f * E
     if kind == "p":
         return f * E / (1.0 - 0.5 * f)
+    if kind == "plus_half":
+        return f * E / (1.0 - f)
     raise ValueError(kind)
 
 
 def bibee_energy(g: Geometry, rq, q, eps_in, eps_out, kind="cfa"):
     return solvation_energy(g, rq, q, bibee_x(g, rq, q, eps_in, eps_out, kind), eps_in)
+
+
+def molecule_energy(verts, tris, rq, q, eps_in, eps_out, method="bem", tol=1e-10, maxit=500, restart=0):
+    """Solvation energy of one molecule (surface mesh plus charges) in
+    kcal/mol: method "bem" solves the full system, "cfa", "p" or "plus_half"
+    takes the BIBEE surface charge."""
+    g = geometry(verts, tris)
+    if method == "bem":
+        x, _ = solve(g, rq, q, eps_in, eps_out, tol=tol, maxit=maxit, restart=restart)
+    else:
+        x = bibee_x(g, rq, q, eps_in, eps_out, method)
+    return solvation_energy(g, rq, q, x, eps_in)
+
+
+def binding_energy(complex_, protein, inhibitor, eps_in, eps_out, method="bem", tol=1e-10):
+    """dG_bind = dG_complex - dG_protein - dG_inhibitor (Section 4.4, eq.
+    binding-free-energy-estimate); each argument is (verts, tris, rq, q).
+    Returns (bind, complex, protein, inhibitor)."""
+    parts = [molecule_energy(*m, eps_in, eps_out, method=method, tol=tol) for m in (complex_, protein, inhibitor)]
+    return (parts[0] - parts[1] - parts[2], parts[0], parts[1], parts[2])
 
 
 def adjoint_grad(g: Geometry, rq, q, x, eps_in, eps_out, tol=1e-10, maxit=500, restart=0):
@@ -258,4 +285,5 @@ __all__ = [
     "K_COULOMB", "build", "Geometry", "geometry", "f_factor", "kappa", "field_B", "apply_A",
     "apply_AT", "apply_Kp", "apply_C", "apply_CT", "apply_BT", "grad_at_points", "assemble_A",
     "SolveInfo", "gmres", "solve", "solvation_energy", "bibee_x", "bibee_energy", "adjoint_grad",
+    "molecule_energy", "binding_energy",
 ]

@@ -23,7 +23,8 @@ from . import build as _build
 # ------------------------------------------------------------ constants
 FP64, FP32, FP32_REFINED = 0, 1, 2
 OP_A, OP_AT, OP_B, OP_BT, OP_C, OP_CT = range(6)
-BIBEE_CFA, BIBEE_P = 0, 1
+BIBEE_CFA, BIBEE_P, BIBEE_PLUS_HALF = 0, 1, 2
+ENERGY_BEM, ENERGY_BIBEE_CFA, ENERGY_BIBEE_P, ENERGY_BIBEE_PLUS_HALF = 0, 1, 2, 3
 MAC_THETA, MAC_ADJACENT = 0, 1
 _STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV", 5: "ESTATE"}
 
@@ -114,10 +115,13 @@ def _load():
     lib.bemfmm_profile_get.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)]
     lib.bemfmm_release_cache.argtypes = []
     lib.bemfmm_profile_select.argtypes = [P, I, I]
+    lib.bemfmm_debug_record.argtypes = [P, I]
+    lib.bemfmm_binding_energy.argtypes = [P, P, P, P, P, P, I, I, D, I, I, ctypes.POINTER(D), P]
     for name in ("bemfmm_build_tree", "bemfmm_set_charges", "bemfmm_tree_destroy", "bemfmm_tree_get_info",
                  "bemfmm_fmm_matvec", "bemfmm_solve_bem", "bemfmm_bibee_energy", "bemfmm_solvation_energy",
                  "bemfmm_adjoint_grad", "bemfmm_tree_export", "bemfmm_debug_expansions", "bemfmm_debug_fields",
-                 "bemfmm_profile", "bemfmm_profile_get", "bemfmm_release_cache", "bemfmm_profile_select"):
+                 "bemfmm_profile", "bemfmm_profile_get", "bemfmm_release_cache", "bemfmm_profile_select",
+                 "bemfmm_debug_record", "bemfmm_binding_energy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -266,6 +270,18 @@ def bibee_energy(tree: Tree, q, kind=BIBEE_CFA, precision=FP32, stream=None) -> 
     return out.value
 
 
+def binding_energy(complex_tree: Tree, q_complex, protein_tree: Tree, q_protein, inhibitor_tree: Tree, q_inhibitor,
+                   method=ENERGY_BEM, precision=FP32_REFINED, tol=1e-6, maxit=300, restart=30, stream=None) -> dict:
+    """bemfmm_binding_energy: dG_bind = dG_complex - dG_protein - dG_inhibitor
+    (kcal/mol), with the three parts."""
+    qs = [_to_dev(q, torch.float64) for q in (q_complex, q_protein, q_inhibitor)]
+    out = (ctypes.c_double * 4)()
+    _check(_load().bemfmm_binding_energy(complex_tree.handle, _ptr(qs[0]), protein_tree.handle, _ptr(qs[1]),
+                                         inhibitor_tree.handle, _ptr(qs[2]), int(method), int(precision), float(tol),
+                                         int(maxit), int(restart), out, _stream(stream)))
+    return {"binding": out[0], "complex": out[1], "protein": out[2], "inhibitor": out[3]}
+
+
 def solvation_energy(tree: Tree, q, x, precision=FP64, stream=None) -> float:
     qd = _to_dev(q, torch.float64)
     xd = _to_dev(x, torch.float64)
@@ -319,6 +335,11 @@ def debug_expansions(tree: Tree, precision: int, which: int) -> np.ndarray:
     return out
 
 
+def debug_record(tree: Tree, enable: bool = True):
+    """bemfmm_debug_record: later products also keep their near and far parts."""
+    _check(_load().bemfmm_debug_record(tree.handle, 1 if enable else 0))
+
+
 def debug_fields(tree: Tree, precision: int, n_targets: int):
     near = np.zeros(n_targets)
     far = np.zeros(n_targets)
@@ -350,6 +371,8 @@ def profile_get(tree: Tree, stage: str):
 
 __all__ = [
     "FP64", "FP32", "FP32_REFINED", "OP_A", "OP_AT", "OP_B", "OP_BT", "OP_C", "OP_CT", "BIBEE_CFA", "BIBEE_P",
+    "BIBEE_PLUS_HALF", "ENERGY_BEM", "ENERGY_BIBEE_CFA", "ENERGY_BIBEE_P", "ENERGY_BIBEE_PLUS_HALF", "binding_energy",
+    "debug_record",
     "MAC_THETA", "MAC_ADJACENT", "Params", "SolveInfo", "Tree", "BemfmmError", "NotConverged", "build_tree",
     "set_charges", "tree_destroy", "fmm_matvec", "solve_bem", "bibee_energy", "solvation_energy", "adjoint_grad",
     "tree_export", "debug_expansions", "debug_fields", "profile", "profile_get", "library_path",

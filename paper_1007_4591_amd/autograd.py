@@ -4,9 +4,11 @@
 A^-1 f B q (kcal/mol) from the FMM-BEM solve; its backward runs the library's
 hand-written adjoint (``bemfmm_adjoint_grad``: one transposed solve A^T y =
 C^T q with a dipole-source FMM, then one FMM for the charge potentials and
-fields) instead of differentiating through the solver.  Only the tree handle
-and the forward solution x are kept between forward and backward; every
-expansion is recomputed (rematerialised) in backward.
+fields) instead of differentiating through the solver.  Only the tree handle,
+the charge values and positions and the forward solution x are kept between
+forward and backward; every expansion is recomputed (rematerialised) in
+backward, after the charges are moved back to the positions of this forward
+(another forward on the same tree may have moved them since).
 
 The triangulated surface is held fixed; ``pos`` moves the charges inside
 their leaf cells of the existing tree (``bemfmm_set_charges``).
@@ -26,7 +28,7 @@ class SolvationEnergy(torch.autograd.Function):
         set_charges(tree, pos)
         x, info = solve_bem(tree, q, tol=tol, maxit=maxit, restart=restart, precision=precision)
         dG = solvation_energy(tree, q, x, precision=precision)
-        ctx.save_for_backward(q, x)
+        ctx.save_for_backward(q, pos, x)
         ctx.tree = tree
         ctx.opts = (tol, maxit, restart, precision)
         ctx.forward_info = info
@@ -34,8 +36,9 @@ class SolvationEnergy(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        q, x = ctx.saved_tensors
+        q, pos, x = ctx.saved_tensors
         tol, maxit, restart, precision = ctx.opts
+        set_charges(ctx.tree, pos)
         want_q, want_pos = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         dq, dpos, _ = adjoint_grad(ctx.tree, q, x, tol=tol, maxit=maxit, restart=restart, precision=precision,
                                    want_dq=want_q, want_dpos=want_pos)

@@ -174,7 +174,8 @@ int bemfmm_bibee_energy(bemfmm_tree *tree, const double *q, int kind, int precis
   return guard([&] {
     Tree *T = check_tree(tree);
     DeviceScope dev_scope(*T);
-    need(kind == BEMFMM_BIBEE_CFA || kind == BEMFMM_BIBEE_P, "unknown BIBEE kind");
+    need(kind == BEMFMM_BIBEE_CFA || kind == BEMFMM_BIBEE_P || kind == BEMFMM_BIBEE_PLUS_HALF, "unknown BIBEE kind");
+    need(precision >= BEMFMM_FP64 && precision <= BEMFMM_FP32_REFINED, "unknown precision");
     need(dG_host != nullptr && (T->Q == 0 || q != nullptr), "q/dG are NULL");
     *dG_host = bibee(*T, q, kind, precision, (hipStream_t)stream);
   });
@@ -198,6 +199,32 @@ int bemfmm_adjoint_grad(bemfmm_tree *tree, const double *q, const double *x, dou
     need(x != nullptr && (T->Q == 0 || q != nullptr), "q/x are NULL");
     need(tol > 0 && maxit >= 1, "tol must be > 0 and maxit >= 1");
     adjoint(*T, q, x, tol, maxit, restart, precision, dG_dq, dG_dpos, info, (hipStream_t)stream);
+  });
+}
+
+int bemfmm_binding_energy(bemfmm_tree *complex_tree, const double *q_complex, bemfmm_tree *protein_tree,
+                          const double *q_protein, bemfmm_tree *inhibitor_tree, const double *q_inhibitor,
+                          int method, int precision, double tol, int maxit, int restart, double *dG_host,
+                          void *stream) {
+  return guard([&] {
+    Tree *T[3] = {check_tree(complex_tree), check_tree(protein_tree), check_tree(inhibitor_tree)};
+    const double *q[3] = {q_complex, q_protein, q_inhibitor};
+    need(dG_host != nullptr, "dG is NULL");
+    need(method >= BEMFMM_ENERGY_BEM && method <= BEMFMM_ENERGY_BIBEE_PLUS_HALF, "unknown energy method");
+    need(precision >= BEMFMM_FP64 && precision <= BEMFMM_FP32_REFINED, "unknown precision");
+    need(method != BEMFMM_ENERGY_BEM || (tol > 0 && maxit >= 1), "tol must be > 0 and maxit >= 1");
+    for (int k = 0; k < 3; ++k) {
+      need(T[k]->Q == 0 || q[k] != nullptr, "charges are NULL");
+      need(T[k]->device == T[0]->device, "the three trees must live on one device");
+    }
+    DeviceScope dev_scope(*T[0]);
+    double e[3];
+    for (int k = 0; k < 3; ++k)
+      e[k] = molecule_energy(*T[k], q[k], method, precision, tol, maxit, restart, (hipStream_t)stream);
+    dG_host[0] = e[0] - e[1] - e[2];
+    dG_host[1] = e[0];
+    dG_host[2] = e[1];
+    dG_host[3] = e[2];
   });
 }
 
@@ -250,6 +277,13 @@ int bemfmm_debug_expansions(bemfmm_tree *tree, int precision, int which, double 
     need(out_host != nullptr, "out is NULL");
     HIP_OK(hipDeviceSynchronize());
     debug_expansions(*T, precision, which, out_host, nullptr);
+  });
+}
+
+int bemfmm_debug_record(bemfmm_tree *tree, int enable) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    T->debug_record = enable != 0;
   });
 }
 

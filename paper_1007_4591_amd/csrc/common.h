@@ -280,6 +280,7 @@ struct Tree {
   bool ev_init = false;
 
   int last_op32 = -1, last_op64 = -1;
+  bool debug_record = false;  // products also write their near and far parts (bemfmm_debug_fields)
 
   ~Tree();
 };
@@ -328,6 +329,9 @@ void solve_bem(Tree &T, const double *q, double *x, double tol, int maxit, int r
                bemfmm_solve_info *info, hipStream_t s);
 double energy(Tree &T, const double *q, const double *x, int precision, hipStream_t s);
 double bibee(Tree &T, const double *q, int kind, int precision, hipStream_t s);
+// solvation energy of one tree by the full BEM solve or a BIBEE variant (bemfmm_energy_method)
+double molecule_energy(Tree &T, const double *q, int method, int precision, double tol, int maxit, int restart,
+                       hipStream_t s);
 void adjoint(Tree &T, const double *q, const double *x, double tol, int maxit, int restart, int precision,
              double *dq, double *dpos, bemfmm_solve_info *info, hipStream_t s);
 double dot_d(Tree &T, const double *a, const double *b, int64_t n, hipStream_t s);

@@ -37,7 +37,8 @@ struct PrecBufs {
   DBuf<char> m2l_out;           // real [nfar * ps]
   DBuf<char> l2l_out;           // real [cells of the largest level * ps]
   DBuf<char> E;                 // real [nleaf * 4 * ps]
-  DBuf<double> dbg_near, dbg_far;  // sorted-order raw fields (debug)
+  DBuf<double> dbg_near, dbg_far;  // sorted-order raw fields (only while debug recording is on)
+  bool dbg_valid = false;          // the last product recorded them
   DBuf<double> near_out;           // near field per target (sorted order)
   int last_tgt = 0;
   bool have = false;
@@ -1341,8 +1342,6 @@ static PrecBufs &bufs(Tree &T, int prec, hipStream_t s) {
     pb->m2l_out.alloc((size_t)std::max<int64_t>(T.nfar, 1) * T.ps * rs);
     pb->l2l_out.alloc((size_t)std::max<int64_t>(T.l2lw.max_cells, 1) * T.ps * rs);
     pb->E.alloc((size_t)T.ncell[T.L] * 4 * T.ps * rs);
-    pb->dbg_near.alloc(npts);
-    pb->dbg_far.alloc(npts);
     pb->near_out.alloc(4 * npts);
     pb->M.zero(s);
     pb->L.zero(s);
@@ -1495,8 +1494,15 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   a.area_scale = rq.area_scale ? 1 : 0;
   a.accumulate = rq.accumulate ? 1 : 0;
   a.y = rq.y;
-  a.dbg_near = B.dbg_near.p;
-  a.dbg_far = B.dbg_far.p;
+  // near and far parts are written only while the caller records them
+  if (T.debug_record) {
+    const int64_t npts = std::max<int64_t>(std::max(T.N, T.Q), 1);
+    B.dbg_near.reserve(npts);
+    B.dbg_far.reserve(npts);
+  }
+  a.dbg_near = T.debug_record ? B.dbg_near.p : nullptr;
+  a.dbg_far = T.debug_record ? B.dbg_far.p : nullptr;
+  B.dbg_valid = T.debug_record;
   a.near_out = B.near_out.p;
   B.last_tgt = rq.tgt;
   // The near field runs on the second stream, forked from the caller's
@@ -1706,6 +1712,7 @@ void debug_expansions(Tree &T, int precision, int which, double *out_host, hipSt
 void debug_fields(Tree &T, int precision, double *near_host, double *far_host, hipStream_t s) {
   PrecBufs *B = (precision == BEMFMM_FP64) ? T.pb64 : T.pb32;
   if (!B || !B->have) BF_THROW(BEMFMM_ESTATE, "no matvec has run at this precision");
+  if (!B->dbg_valid) BF_THROW(BEMFMM_ESTATE, "the last product at this precision ran without bemfmm_debug_record");
   const int64_t nt = (B->last_tgt == TGT_CHARGE) ? T.Q : T.N;
   std::vector<double> ns(nt), fs(nt);
   std::vector<int32_t> perm(nt);

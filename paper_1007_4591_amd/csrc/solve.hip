@@ -385,10 +385,25 @@ double bibee(Tree &T, const double *q, int kind, int precision, hipStream_t s) {
   const double f = 1.0 - T.prm.eps_in / T.prm.eps_out;
   struct { double *p; } xh{T.buf("bb_x", n)};
   op_apply(T, BEMFMM_OP_B, precision, q, xh.p, s);
-  const double scale = (kind == BEMFMM_BIBEE_P) ? f / (1.0 - 0.5 * f) : f;
+  // K' replaced by -1/2 (CFA), 0 (P) or +1/2 times the identity, with the
+  // interior jump +1/2 kept: x (1 - f (lambda + 1/2)) = f E
+  const double scale = (kind == BEMFMM_BIBEE_P) ? f / (1.0 - 0.5 * f) : (kind == BEMFMM_BIBEE_PLUS_HALF) ? f / (1.0 - f) : f;
   k_scale<<<cdiv(n, 256), 256, 0, s>>>(xh.p, xh.p, scale, n);
   LAUNCH_OK();
   return energy(T, q, xh.p, precision, s);
+}
+
+double molecule_energy(Tree &T, const double *q, int method, int precision, double tol, int maxit, int restart,
+                       hipStream_t s) {
+  if (method == BEMFMM_ENERGY_BEM) {
+    double *x = T.buf("me_x", T.N);
+    solve_bem(T, q, x, tol, maxit, restart, precision, nullptr, s);
+    return energy(T, q, x, precision == BEMFMM_FP32 ? BEMFMM_FP32 : BEMFMM_FP64, s);
+  }
+  const int kind = method == BEMFMM_ENERGY_BIBEE_CFA ? BEMFMM_BIBEE_CFA
+                   : method == BEMFMM_ENERGY_BIBEE_P ? BEMFMM_BIBEE_P
+                                                     : BEMFMM_BIBEE_PLUS_HALF;
+  return bibee(T, q, kind, precision, s);
 }
 
 void adjoint(Tree &T, const double *q, const double *x, double tol, int maxit, int restart, int precision,

@@ -1311,11 +1311,14 @@ void set_charges(Tree &T, const double *qpos, hipStream_t s) {
   DBuf<double4> q64;
   q32.alloc(nq);
   q64.alloc(nq);
+  // a charge may leave its leaf box by 1/1000 of the side at most: the near
+  // and far lists were built for points inside the leaf boxes, and this
+  // keeps the MAC's separation ratio within 0.2% of its design value
   k_gather_charges<<<cdiv(nq, TB), TB, 0, s>>>(T.qperm.p, T.qleaf.p, nq, T.cxyz.p + T.coff[T.L], T.lo[0], T.lo[1],
-                                               T.lo[2], sL, tmp.p, q32.p, q64.p, 0.75 * sL, err.p);
+                                               T.lo[2], sL, tmp.p, q32.p, q64.p, (0.5 + 1e-3) * sL, err.p);
   LAUNCH_OK();
   if (read_err(err, s) & 16)
-    BF_THROW(BEMFMM_EINVAL, "set_charges: a charge left its leaf cell by more than a quarter side; rebuild the tree");
+    BF_THROW(BEMFMM_EINVAL, "set_charges: a charge left its leaf cell (by more than 1/1000 of its side); rebuild the tree");
   copy_d2d(T.qpos.p, tmp.p, 3 * nq, s);
   copy_d2d(T.q32pos.p, q32.p, nq, s);
   copy_d2d(T.q64pos.p, q64.p, nq, s);

@@ -9,7 +9,7 @@ The surfaces stand in for the paper's molecular surfaces (Section 4 and the
 Appendix use PDB structures meshed with MSMS, which are not available): a
 protein-scale closed surface of 1e4..1e6 flat triangles, with charges inside
 it, and many randomly rotated copies on a Cartesian lattice for the crowded
-protein-solution workload of Section 4.4.
+protein-solution workload of Section 4.5.
 
 Conventions
 -----------

@@ -32,3 +32,13 @@ def rel_l2(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def leaf_boxes(tree, pos):
+    """Lower and upper corners of the leaf box of each point (from the tree's
+    root cube and leaf level; a point's leaf is fixed when the tree is built)."""
+    inf = tree.info
+    sL = inf["side"] / 2 ** inf["leaf_level"]
+    lo = np.asarray(inf["lo"])
+    c = np.floor((np.asarray(pos) - lo) / sL)
+    return lo + c * sL, lo + (c + 1) * sL, sL

@@ -30,26 +30,31 @@ def test_source_hash_ignores_comments_and_whitespace(tmp_path):
 
 
 def test_traffic_reported_only_for_the_profiled_source(tmp_path):
-    """A copy of bench.py beside a fake source and a fake counter summary:
-    the figure comes back while the summary's hash is that of the source,
-    and None once the source's code changes (a comment change keeps it)."""
+    """A copy of bench.py beside fake library sources and a fake counter
+    summary: the figure comes back while the summary's hash is that of the
+    sources, and None once any of them changes its code (a comment change
+    keeps it)."""
     shutil.copy(os.path.join(ROOT, "bench.py"), tmp_path / "bench.py")
-    (tmp_path / "paper_1007_4591_amd" / "csrc").mkdir(parents=True)
-    src = tmp_path / "paper_1007_4591_amd" / "csrc" / "fmm.hip"
-    src.write_text("__global__ void k(float *y) { y[0] = 1.f; }\n")
+    csrc = tmp_path / "paper_1007_4591_amd" / "csrc"
+    csrc.mkdir(parents=True)
     bench = _load_bench(str(tmp_path / "bench.py"))
-    sha = bench.kernel_source_hash(str(src))
+    for name in bench.TRAFFIC_SOURCES:
+        (csrc / name).write_text(f"// {name}\nint v_{name.replace('.', '_')} = 1;\n")
+    src = csrc / "fmm.hip"
+    src.write_text("__global__ void k(float *y) { y[0] = 1.f; }\n")
+    sha = bench.library_source_hash()
     (tmp_path / "profiles").mkdir()
-    (tmp_path / "profiles" / "pmc_traffic_blobby-L8.md").write_text(
-        "| kernel | fetch bytes | write bytes | total bytes | fmm.hip code sha256 | launches |\n"
+    (tmp_path / "profiles" / "pmc_traffic_crowded.md").write_text(
+        "| kernel | fetch bytes | write bytes | total bytes | code sha256 | launches |\n"
         "|---|---|---|---|---|---|\n"
         f"| `k<float, 0>` | 100 | 20 | 120 | {sha} | 3 of 3 |\n")
-    assert bench.pmc_traffic("k<float, 0>") == 120.0
-    assert bench.pmc_traffic("k<float, 1>") is None
+    assert bench.pmc_traffic("k<float, 0>", "crowded") == 120.0
+    assert bench.pmc_traffic("k<float, 1>", "crowded") is None
+    assert bench.pmc_traffic("k<float, 0>", "blobby") is None
     src.write_text("__global__ void k(float *y) { y[0] = 1.f; }  // a comment\n")
-    assert bench.pmc_traffic("k<float, 0>") == 120.0
-    src.write_text("__global__ void k(float *y) { y[0] = 2.f; }\n")
-    assert bench.pmc_traffic("k<float, 0>") is None
+    assert bench.pmc_traffic("k<float, 0>", "crowded") == 120.0
+    (csrc / "tree_build.hip").write_text("int v = 2;\n")
+    assert bench.pmc_traffic("k<float, 0>", "crowded") is None
 
 
 def test_more_than_one_gpu_is_refused():

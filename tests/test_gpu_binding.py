@@ -1,7 +1,8 @@
-"""Binding-energy composition (Section 4.3): two molecules as the
-"complex" (two closed surfaces, all charges), each alone as the parts;
-compared with the dense oracle's three energies, and the interaction term
-vanishing as the molecules separate."""
+"""Binding energy (Section 4.4, eq. binding-free-energy-estimate) through
+bemfmm_binding_energy: two molecules as the "complex" (two closed surfaces,
+all charges), each alone as the parts; compared with the dense oracle's
+three energies for the full BEM and every BIBEE variant, and the
+interaction term vanishing as the molecules separate."""
 import numpy as np
 import pytest
 
@@ -43,6 +44,31 @@ def test_binding_matches_dense():
     for k in ("complex", "protein", "inhibitor"):
         assert abs(got[k] - want[k]) <= 1e-5 * abs(want[k])
     assert abs(got["binding"] - want["binding"]) <= 1e-5 * abs(want["complex"])
+
+
+@pytest.mark.parametrize("method", ["cfa", "p", "plus_half"])
+def test_binding_bibee_matches_dense(method):
+    from paper_1007_4591_amd.binding import binding_energy
+    B = lib()
+    c, p, i = _pair(40.0)
+    for prec, tol in ((0, 1e-5), (1, 1e-4)):
+        got = binding_energy(c, p, i, method=method, params=B.Params(ncrit=16), precision=prec)
+        want = oracle.binding_energy(*[(m.verts, m.tris, m.charge_pos, m.q) for m in (c, p, i)], 4.0, 80.0,
+                                     method=method)
+        print(f"[binding-{method}] prec={prec} got={got} want={want}", flush=True)
+        for k, w in zip(("binding", "complex", "protein", "inhibitor"), want):
+            assert abs(got[k] - w) <= tol * abs(want[1])
+
+
+def test_binding_rejects_bad_method():
+    B = lib()
+    a = synth.born(2)
+    t = B.build_tree(a.verts, a.tris, a.charge_pos, B.Params())
+    with pytest.raises(B.BemfmmError):
+        B.binding_energy(t, a.q, t, a.q, t, a.q, method=4)
+    # one tree for all three parts: complex - 2 x itself = -dG
+    out = B.binding_energy(t, a.q, t, a.q, t, a.q, method=B.ENERGY_BIBEE_CFA, precision=0)
+    assert out["binding"] == pytest.approx(-out["complex"], rel=1e-12)
 
 
 def test_binding_vanishes_with_separation():

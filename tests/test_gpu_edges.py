@@ -9,7 +9,7 @@ import pytest
 import oracle
 import synth
 
-from gpu_common import requires_gpu, lib, dev, host, rel_l2
+from gpu_common import requires_gpu, lib, dev, host, rel_l2, leaf_boxes
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 EPS_IN, EPS_OUT = 4.0, 80.0
@@ -125,3 +125,41 @@ def test_theta_extremes():
     assert errs[0.3] < errs[0.5] < errs[1.0]
     assert errs[0.3] <= 1e-7 and errs[0.5] <= 1e-5 and errs[1.0] <= 5e-2
     assert max(gap32.values()) <= 2e-6
+
+
+def test_set_charges_limits():
+    """bemfmm_set_charges keeps the tree: charges pushed to 0.9/1000 of a
+    leaf side beyond their leaf boxes are accepted and every charge operator
+    still matches the dense oracle at the moved positions; a charge moved
+    0.1 side beyond its box is rejected (EINVAL) and leaves the charges as
+    they were."""
+    B = lib()
+    p = synth.differentiation(4)
+    g = oracle.geometry(p.verts, p.tris)
+    t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params())
+    lo, hi, sL = leaf_boxes(t, p.charge_pos)
+    rng = np.random.default_rng(12)
+    x = rng.normal(size=p.n_panels)
+    before = host(B.fmm_matvec(t, B.OP_C, B.FP64, dev(x)))
+    bad = p.charge_pos.copy()
+    bad[7, 0] = hi[7, 0] + 0.1 * sL
+    with pytest.raises(B.BemfmmError) as ei:
+        B.set_charges(t, dev(bad))
+    assert ei.value.code == 1
+    np.testing.assert_array_equal(host(B.fmm_matvec(t, B.OP_C, B.FP64, dev(x))), before)
+    # every charge to just outside one face of its box
+    moved = p.charge_pos.copy()
+    axis = rng.integers(3, size=p.n_charges)
+    side = rng.integers(2, size=p.n_charges)
+    k = np.arange(p.n_charges)
+    moved[k, axis] = np.where(side == 1, hi[k, axis] + 0.9e-3 * sL, lo[k, axis] - 0.9e-3 * sL)
+    B.set_charges(t, dev(moved))
+    qv, y = rng.normal(size=p.n_charges), rng.normal(size=p.n_panels)
+    want = {B.OP_B: oracle.field_B(g, moved, qv), B.OP_BT: oracle.apply_BT(g, moved, y),
+            B.OP_C: oracle.apply_C(g, moved, x), B.OP_CT: oracle.apply_CT(g, moved, qv)}
+    ins = {B.OP_B: qv, B.OP_BT: y, B.OP_C: x, B.OP_CT: qv}
+    for prec in (0, 1):
+        for op, w in want.items():
+            e = rel_l2(host(B.fmm_matvec(t, op, prec, dev(ins[op]))), w)
+            print(f"[set_charges] op={op} prec={prec} err={e:.2e}", flush=True)
+            assert e <= 1e-5

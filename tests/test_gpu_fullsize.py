@@ -41,10 +41,50 @@ def test_blobby_full_sampled_rows():
         assert errs[prec][0] <= 1e-5 and errs[prec][1] <= 1e-5
 
 
+def _sub(g, rows):
+    return oracle.Geometry(g.c[rows], g.n[rows], g.a[rows])
+
+
 def test_crowded_full_sampled_rows():
+    """Crowded system (512 molecules, 10,485,760 panels, 512,000 charges):
+    all six operators on sampled rows (panel rows through a sub-geometry of
+    the sampled targets, charge rows through the sampled charges); then the
+    plain FP64 and the FP32-refined solves to 1e-6 agree in energy and the
+    refined solution's residual holds on sampled dense rows.  The dense
+    energy itself is out of reach here (parity partly unpinned, bounded by
+    the sampled rows)."""
     errs, t = _sampled_rows("crowded-512x-L5", lambda: synth.crowded(), 128, 4)
     for prec in (0, 1):
         assert errs[prec][0] <= 1e-5 and errs[prec][1] <= 1e-5
+    B = lib()
+    p = synth.crowded()
+    g = oracle.geometry(p.verts, p.tris)
+    rng = np.random.default_rng(41)
+    prow = np.sort(rng.choice(p.n_panels, size=96, replace=False))
+    qrow = np.sort(rng.choice(p.n_charges, size=96, replace=False))
+    x, qv = rng.normal(size=p.n_panels), rng.normal(size=p.n_charges)
+    sub = _sub(g, prow)
+    want = {B.OP_B: oracle.field_B(sub, p.charge_pos, qv), B.OP_CT: oracle.apply_CT(sub, p.charge_pos, qv),
+            B.OP_C: oracle.apply_C(g, p.charge_pos[qrow], x), B.OP_BT: oracle.apply_BT(g, p.charge_pos[qrow], x)}
+    ins = {B.OP_B: qv, B.OP_CT: qv, B.OP_C: x, B.OP_BT: x}
+    rows = {B.OP_B: prow, B.OP_CT: prow, B.OP_C: qrow, B.OP_BT: qrow}
+    for prec in (1, 0):
+        for op, w in want.items():
+            got = host(B.fmm_matvec(t, op, prec, dev(ins[op])))[rows[op]]
+            e = rel_l2(got, w)
+            print(f"    crowded op={op} prec={prec} err={e:.2e}", flush=True)
+            assert e <= 1e-5
+    x64, i64 = B.solve_bem(t, dev(p.q), tol=1e-6, maxit=300, precision=0)
+    x32, i32 = B.solve_bem(t, dev(p.q), tol=1e-6, maxit=300, precision=2)
+    e64 = B.solvation_energy(t, dev(p.q), x64)
+    e32 = B.solvation_energy(t, dev(p.q), x32)
+    print(f"[crowded-solve] fp64 {e64:.8f} ({i64.iters} it, {i64.seconds:.3f} s) refined {e32:.8f} "
+          f"({i32.iters} it, {i32.outer_iters} outer, {i32.seconds:.3f} s)", flush=True)
+    assert i64.converged and i32.converged
+    assert abs(e32 - e64) <= 1e-5 * abs(e64)
+    rhs = F * oracle.field_B(sub, p.charge_pos, p.q)
+    r = oracle.apply_A(g, F, host(x32), rows=prow) - rhs
+    assert np.linalg.norm(r) <= 1e-5 * np.linalg.norm(rhs)
 
 
 def test_blobby_full_bibee_and_solve():
@@ -77,9 +117,20 @@ def test_blobby_full_bibee_and_solve():
 
 
 def test_differentiation_fd_20_components():
-    """dG/dq and dG/dr at the level-7 differentiation workload vs central
-    differences (h = 1e-4 e and 1e-4 A) on 20 seeded components, on a frozen
-    tree with FP64 solves to 1e-11."""
+    """dG/dq and dG/dr at the level-7 differentiation workload (327,680
+    panels, 2000 charges) vs central differences (h = 1e-4 e and 1e-4 A) on
+    20 seeded components, on a frozen tree, for the FP64 and the
+    FP32-refined gradients.  The differences use FP64 solves to 1e-12.
+
+    Error budget of a difference, relative to the largest gradient entry:
+    dG is quadratic in q, so the charge differences are exact but for the
+    solve (a residual tau moves dG by about tau |dG|, giving tau |dG| / h =
+    5e-6 absolute against entries of order 100-1000); the position
+    differences add h^2 |d3 dG| / 6, about (h / d)^2 = 1e-8 relative for a
+    charge d >= 1 A from the nearest panel; the adjoint's FMM operators differ
+    from the transposes of the forward's by the FMM error (about 1e-8).  The
+    refined gradient adds its solves' tolerance (1e-9).  Bound: 1e-6 for
+    both, against the gradient's largest entry of each kind."""
     B = lib()
     p = synth.differentiation(7)
     t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params())
@@ -88,34 +139,38 @@ def test_differentiation_fd_20_components():
 
     def energy(qv, pv):
         B.set_charges(t, dev(pv))
-        x, _ = B.solve_bem(t, dev(qv), tol=1e-11, maxit=400, precision=0)
+        x, _ = B.solve_bem(t, dev(qv), tol=1e-12, maxit=400, precision=0)
         return B.solvation_energy(t, dev(qv), x)
 
     B.set_charges(t, dev(pos))
-    x, _ = B.solve_bem(t, dev(q), tol=1e-11, maxit=400, precision=0)
-    dq, dpos, _ = B.adjoint_grad(t, dev(q), x, tol=1e-11, maxit=400, precision=0)
-    dq, dpos = host(dq), host(dpos)
+    grads = {}
+    for prec, tol in ((0, 1e-11), (2, 1e-9)):
+        x, _ = B.solve_bem(t, dev(q), tol=tol, maxit=400, precision=prec)
+        dq, dpos, _ = B.adjoint_grad(t, dev(q), x, tol=tol, maxit=400, precision=prec)
+        grads[prec] = (host(dq), host(dpos))
     rng = np.random.default_rng(50)
     comps = rng.choice(p.n_charges * 4, size=20, replace=False)
     h = 1e-4
-    worst_q = worst_r = 0.0
+    worst = {0: [0.0, 0.0], 2: [0.0, 0.0]}
     for c in comps:
         k, d = divmod(int(c), 4)
         if d == 3:
             qp = q.copy(); qp[k] += h
             qm = q.copy(); qm[k] -= h
             fd = (energy(qp, pos) - energy(qm, pos)) / (2 * h)
-            err = abs(dq[k] - fd) / max(abs(fd), 1e-3)
-            worst_q = max(worst_q, err)
+            for prec, (dq, _) in grads.items():
+                worst[prec][0] = max(worst[prec][0], abs(dq[k] - fd) / np.abs(dq).max())
         else:
             pp = pos.copy(); pp[k, d] += h
             pm = pos.copy(); pm[k, d] -= h
             fd = (energy(q, pp) - energy(q, pm)) / (2 * h)
-            err = abs(dpos[k, d] - fd) / max(abs(fd), 1e-2)
-            worst_r = max(worst_r, err)
+            for prec, (_, dpos) in grads.items():
+                worst[prec][1] = max(worst[prec][1], abs(dpos[k, d] - fd) / np.abs(dpos).max())
     B.set_charges(t, dev(pos))
-    print(f"[fd] worst rel err dq={worst_q:.2e} dpos={worst_r:.2e}", flush=True)
-    assert worst_q <= 1e-4 and worst_r <= 1e-2
+    print(f"[fd] worst err vs max |grad|: fp64 dq={worst[0][0]:.2e} dpos={worst[0][1]:.2e}; "
+          f"refined dq={worst[2][0]:.2e} dpos={worst[2][1]:.2e}", flush=True)
+    for prec in (0, 2):
+        assert worst[prec][0] <= 1e-6 and worst[prec][1] <= 1e-6
 
 
 def test_rotation_translation_invariance():

@@ -145,7 +145,14 @@ def test_near_and_far_fields(prec):
     x = rng.normal(size=p.n_panels)
     t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params(ncrit=16))
     B.fmm_matvec(t, 0, prec, dev(x))
+    with pytest.raises(B.BemfmmError):  # not recorded
+        B.debug_fields(t, prec, p.n_panels)
+    B.debug_record(t, True)
+    y_rec = host(B.fmm_matvec(t, 0, prec, dev(x)))
     near, far = B.debug_fields(t, prec, p.n_panels)
+    B.debug_record(t, False)
+    # recording changes nothing in the product itself
+    np.testing.assert_array_equal(y_rec, host(B.fmm_matvec(t, 0, prec, dev(x))))
     ex = B.tree_export(t)
     perm = ex["panel_perm"]
     L = ex["info"]["leaf_level"]

@@ -127,6 +127,57 @@ def test_kirkwood_series_and_bibee_bounds():
     assert errs_cfa[0] > errs_cfa[1] > errs_cfa[2] and errs_cfa[2] < 0.01
 
 
+@pytest.mark.parametrize("kind", ["cfa", "p", "plus_half"])
+def test_bibee_variants_sphere_series(kind):
+    """Each BIBEE variant of Section 2.2 (the principal-value operator
+    replaced by -1/2, 0 or +1/2 times the identity) against its own sphere
+    series: the discrete energy converges at O(h^2), about 4x per level.  A
+    wrong scale (say 1 - f in place of 1 - f/2) is off by a factor of ten."""
+    errs = []
+    for L in (2, 3, 4):
+        p = synth.kirkwood(L, n_charges=20)
+        g = oracle.geometry(p.verts, p.tris)
+        got = oracle.bibee_energy(g, p.charge_pos, p.q, EPS_IN, EPS_OUT, kind)
+        want = cf.sphere_energy(p.charge_pos, p.q, 20.0, EPS_IN, EPS_OUT, kind)
+        errs.append(abs(got - want) / abs(want))
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0
+    assert errs[2] < 0.01
+
+
+def test_bibee_series_ordering_and_born():
+    """Continuum series: the n = 0 term of the CFA series is the Born term
+    (CFA exact for a centred charge), and the variants order as
+    plus_half <= P <= exact <= CFA for charges inside a sphere."""
+    p = synth.kirkwood(3, n_charges=20)
+    e = {k: cf.sphere_energy(p.charge_pos, p.q, 20.0, EPS_IN, EPS_OUT, k) for k in ("cfa", "p", "plus_half", "exact")}
+    assert e["plus_half"] <= e["p"] <= e["exact"] <= e["cfa"]
+    born = cf.born(1.0, 2.0, EPS_IN, EPS_OUT)
+    assert cf.sphere_energy(np.zeros((1, 3)), [1.0], 2.0, EPS_IN, EPS_OUT, "exact") == pytest.approx(born, rel=1e-14)
+
+
+def test_binding_composition_on_one_sphere():
+    """Binding (Section 4.4): with protein, inhibitor and complex sharing one
+    spherical surface (charges A, B and A + B), dG_bind is the cross term of
+    the reaction-field series, K q_A^T M q_B, for the full BEM and for every
+    BIBEE variant; the discrete result converges to it with the mesh."""
+    rng = np.random.default_rng(7)
+    for kind, key in (("bem", "exact"), ("cfa", "cfa"), ("p", "p")):
+        errs = []
+        for L in (3, 4):
+            p = synth.kirkwood(L, n_charges=12)
+            a, b = p.charge_pos[:6], p.charge_pos[6:]
+            qa, qb = p.q[:6], p.q[6:] + rng.uniform(-0.1, 0.1, 6)
+            mol = lambda pos, q: (p.verts, p.tris, pos, q)  # noqa: E731
+            bind, c, pe, ie = oracle.binding_energy(mol(np.vstack([a, b]), np.concatenate([qa, qb])), mol(a, qa),
+                                                    mol(b, qb), EPS_IN, EPS_OUT, method=kind)
+            assert bind == pytest.approx(c - pe - ie, rel=1e-12, abs=1e-12)
+            both = cf.sphere_energy(np.vstack([a, b]), np.concatenate([qa, qb]), 20.0, EPS_IN, EPS_OUT, key)
+            want = both - cf.sphere_energy(a, qa, 20.0, EPS_IN, EPS_OUT, key) - \
+                cf.sphere_energy(b, qb, 20.0, EPS_IN, EPS_OUT, key)
+            errs.append(abs(bind - want) / abs(want))
+        assert errs[1] < errs[0] and errs[1] < 0.05, (kind, errs)
+
+
 def test_gmres_matches_lapack():
     p = synth.kirkwood(3, n_charges=20)
     g = oracle.geometry(p.verts, p.tris)
