@@ -169,6 +169,26 @@ int bemfmm_build_tree(const double *verts, int64_t nv, const int32_t *tris, int6
  * guarantee the MAC's separation); the charges are then left unchanged. */
 int bemfmm_set_charges(bemfmm_tree *tree, const double *charge_pos, void *stream);
 
+/* Bytes of the fixed per-device scratch array of bemfmm_set_charges_noalloc
+ * (a 256-byte error word, then 16 + 32 bytes of staged positions per
+ * charge): it holds up to 699,040 charges. */
+#define BEMFMM_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or optimisation loops, harnesses that forbid
+ * hipMalloc): bemfmm_set_charges with the same arguments, checks and
+ * results, bitwise, that allocates nothing.  Its error word and staged
+ * positions live in a fixed library array of BEMFMM_NOALLOC_SCRATCH_BYTES
+ * that every device the library runs on holds until the process ends, and
+ * it reads charge_pos in place (the caller keeps it valid until the call
+ * returns; the call synchronises `stream`).  EINVAL, with the tree
+ * unchanged, if the tree holds more than 699,040 charges (use
+ * bemfmm_set_charges), or in bemfmm_set_charges' cases.  Every call on one
+ * GPU shares that GPU's array, which keeps the last call's contents: calls
+ * that overlap on one GPU (two host threads, or two streams) race, so
+ * serialise them. */
+int bemfmm_set_charges_noalloc(bemfmm_tree *tree, const double *charge_pos, void *stream);
+
 int bemfmm_tree_destroy(bemfmm_tree *tree);
 
 /* Sizes of the built tree (host struct). */

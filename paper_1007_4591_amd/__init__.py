@@ -100,6 +100,7 @@ def _load():
     P, I64, I, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     lib.bemfmm_build_tree.argtypes = [P, I64, P, I64, P, I64, ctypes.POINTER(_Params), P, ctypes.POINTER(P)]
     lib.bemfmm_set_charges.argtypes = [P, P, P]
+    lib.bemfmm_set_charges_noalloc.argtypes = [P, P, P]
     lib.bemfmm_tree_destroy.argtypes = [P]
     lib.bemfmm_tree_get_info.argtypes = [P, ctypes.POINTER(_TreeInfo)]
     lib.bemfmm_fmm_matvec.argtypes = [P, I, I, P, P, P]
@@ -117,7 +118,7 @@ def _load():
     lib.bemfmm_profile_select.argtypes = [P, I, I]
     lib.bemfmm_debug_record.argtypes = [P, I]
     lib.bemfmm_binding_energy.argtypes = [P, P, P, P, P, P, I, I, D, I, I, ctypes.POINTER(D), P]
-    for name in ("bemfmm_build_tree", "bemfmm_set_charges", "bemfmm_tree_destroy", "bemfmm_tree_get_info",
+    for name in ("bemfmm_build_tree", "bemfmm_set_charges", "bemfmm_set_charges_noalloc", "bemfmm_tree_destroy", "bemfmm_tree_get_info",
                  "bemfmm_fmm_matvec", "bemfmm_solve_bem", "bemfmm_bibee_energy", "bemfmm_solvation_energy",
                  "bemfmm_adjoint_grad", "bemfmm_tree_export", "bemfmm_debug_expansions", "bemfmm_debug_fields",
                  "bemfmm_profile", "bemfmm_profile_get", "bemfmm_release_cache", "bemfmm_profile_select",
@@ -216,6 +217,13 @@ def set_charges(tree: Tree, charge_pos, stream=None):
     """bemfmm_set_charges: move charges inside their leaf cells."""
     q = _to_dev(charge_pos, torch.float64)
     _check(_load().bemfmm_set_charges(tree.handle, _ptr(q), _stream(stream)))
+
+
+def set_charges_noalloc(tree: Tree, charge_pos, stream=None):
+    """bemfmm_set_charges_noalloc: set_charges without device allocation
+    (the staging lives in the library's fixed per-device array)."""
+    q = _to_dev(charge_pos, torch.float64)
+    _check(_load().bemfmm_set_charges_noalloc(tree.handle, _ptr(q), _stream(stream)))
 
 
 def tree_destroy(tree: Tree):
@@ -374,7 +382,7 @@ __all__ = [
     "BIBEE_PLUS_HALF", "ENERGY_BEM", "ENERGY_BIBEE_CFA", "ENERGY_BIBEE_P", "ENERGY_BIBEE_PLUS_HALF", "binding_energy",
     "debug_record",
     "MAC_THETA", "MAC_ADJACENT", "Params", "SolveInfo", "Tree", "BemfmmError", "NotConverged", "build_tree",
-    "set_charges", "tree_destroy", "fmm_matvec", "solve_bem", "bibee_energy", "solvation_energy", "adjoint_grad",
+    "set_charges", "set_charges_noalloc", "tree_destroy", "fmm_matvec", "solve_bem", "bibee_energy", "solvation_energy", "adjoint_grad",
     "tree_export", "debug_expansions", "debug_fields", "profile", "profile_get", "library_path",
     "release_cache", "profile_select",
 ]

@@ -115,6 +115,15 @@ int bemfmm_set_charges(bemfmm_tree *tree, const double *charge_pos, void *stream
   });
 }
 
+int bemfmm_set_charges_noalloc(bemfmm_tree *tree, const double *charge_pos, void *stream) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
+    need(T->Q == 0 || charge_pos, "charge_pos is NULL");
+    set_charges_noalloc(*T, charge_pos, (hipStream_t)stream);
+  });
+}
+
 int bemfmm_tree_destroy(bemfmm_tree *tree) {
   return guard([&] {
     Tree *T = check_tree(tree);

@@ -291,6 +291,8 @@ Tree *check_tree(const bemfmm_tree *t);
 void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
                 const double *qpos, int64_t nq, hipStream_t s);
 void set_charges(Tree &T, const double *qpos, hipStream_t s);
+void set_charges_noalloc(Tree &T, const double *qpos, hipStream_t s);
+int64_t noalloc_max_charges();
 void upload_tables(Tree &T, hipStream_t s);
 
 // primitives (tree_build.hip)

@@ -13,9 +13,17 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 
 #include "common.h"
+
+// Device memory of the allocation-free bemfmm_set_charges_noalloc: one error
+// word, then the staged leaf-relative FP32 and FP64 charge positions.  Every
+// device the library runs on holds its own copy until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// the current device (the array's name is not a device address on the host).
+static __device__ __align__(256) unsigned char scratch[BEMFMM_NOALLOC_SCRATCH_BYTES];
 
 namespace bemfmm {
 
@@ -1290,6 +1298,78 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     if (!cq.empty())
       HIP_OK(hipMemcpyAsync(T.chunk_q.p, cq.data(), cq.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   }
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+namespace {
+
+__global__ void k_zero_i32(int *p) { *p = 0; }
+
+int read_err_ptr(const int *e, hipStream_t s) {
+  int h = 0;
+  HIP_OK(hipMemcpyAsync(&h, e, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return h;
+}
+
+// Device address of `scratch` per device, taken once per device with that
+// device current (the caller's DeviceScope makes the tree's device current).
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+unsigned char *scratch_ptr() {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) BF_THROW(BEMFMM_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void *p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) BF_THROW(BEMFMM_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+    scratch_dev[dev] = p;
+  }
+  return static_cast<unsigned char *>(scratch_dev[dev]);
+}
+
+}  // namespace
+
+int64_t noalloc_max_charges() {
+  // error word (256 B), then Q float4 and Q double4, each block 256-B aligned
+  return (int64_t)((BEMFMM_NOALLOC_SCRATCH_BYTES - 2 * 256) / (sizeof(float4) + sizeof(double4)));
+}
+
+// set_charges without device allocation: the same kernels and checks, with
+// the error word and the staged positions in `scratch` and the caller's
+// positions read in place.  The tree is changed only after both checks pass.
+void set_charges_noalloc(Tree &T, const double *qpos, hipStream_t s) {
+  const int TB = 256;
+  const int64_t nq = T.Q;
+  if (nq == 0) return;
+  if (nq > noalloc_max_charges())
+    BF_THROW(BEMFMM_EINVAL, "set_charges_noalloc: " + std::to_string(nq) + " charges exceed the " +
+                                std::to_string(noalloc_max_charges()) + " its fixed scratch holds; use bemfmm_set_charges");
+  unsigned char *base = scratch_ptr();
+  int *err = reinterpret_cast<int *>(base);
+  float4 *q32 = reinterpret_cast<float4 *>(base + 256);
+  const size_t off64 = (256 + (size_t)nq * sizeof(float4) + 255) / 256 * 256;
+  double4 *q64 = reinterpret_cast<double4 *>(base + off64);
+  if (off64 + (size_t)nq * sizeof(double4) > BEMFMM_NOALLOC_SCRATCH_BYTES)
+    BF_THROW(BEMFMM_EDEVICE, "set_charges_noalloc: scratch layout overflow");
+  k_zero_i32<<<1, 1, 0, s>>>(err);
+  LAUNCH_OK();
+  k_check_points<<<cdiv(nq, TB), TB, 0, s>>>(qpos, nq, err);
+  LAUNCH_OK();
+  if (read_err_ptr(err, s) & 4) BF_THROW(BEMFMM_EINVAL, "non-finite charge position");
+  const double sL = T.side / double(1 << T.L);
+  k_gather_charges<<<cdiv(nq, TB), TB, 0, s>>>(T.qperm.p, T.qleaf.p, nq, T.cxyz.p + T.coff[T.L], T.lo[0], T.lo[1],
+                                               T.lo[2], sL, qpos, q32, q64, (0.5 + 1e-3) * sL, err);
+  LAUNCH_OK();
+  if (read_err_ptr(err, s) & 16)
+    BF_THROW(BEMFMM_EINVAL, "set_charges: a charge left its leaf cell (by more than 1/1000 of its side); rebuild the tree");
+  copy_d2d(T.qpos.p, qpos, 3 * nq, s);
+  copy_d2d(T.q32pos.p, q32, nq, s);
+  copy_d2d(T.q64pos.p, q64, nq, s);
   HIP_OK(hipStreamSynchronize(s));
 }
 
