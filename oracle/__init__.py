@@ -15,6 +15,9 @@ Contents
                        their definitions (brute force).
 * ``harmonics``     -- solid harmonics and multipole / local expansions by
                        their definitions (scipy Legendre functions).
+* ``panel_integrals`` -- exact integrals of the Green's function and its
+                       gradient over flat triangles, and the near-quadrature
+                       K' (exact integrals for close panel pairs).
 """
 from .dense import *  # noqa: F401,F403
-from . import closed_forms, tree, harmonics  # noqa: F401
+from . import closed_forms, tree, harmonics, panel_integrals  # noqa: F401
