@@ -123,6 +123,15 @@ typedef struct {
   int mac;        /* bemfmm_mac */
   double eps_in;  /* solute permittivity > 0 */
   double eps_out; /* solvent permittivity > 0 */
+  double near_quad; /* 0: one centroid point for every panel pair (Section 2.1).
+                       nu in (0, 16]: near quadrature -- the K' entry of a panel
+                       pair with |c_i - c_j| < nu rho_j (rho_j: the largest
+                       distance from c_j to a vertex of panel j) takes the exact
+                       integral over flat panel j (Section 2.1, discretisation
+                       paragraph: analytic integrals for planar elements); used
+                       by A and A^T and everything built on them.  EINVAL if such
+                       a pair could fall outside the near field (then lower nu
+                       or raise ncrit). */
 } bemfmm_params;
 
 typedef struct {
@@ -145,6 +154,7 @@ typedef struct {
   int64_t p2p_pairs_panels; /* sum over near cell pairs of n_t * n_s (panels -> panels) */
   double lo[3];             /* root cube corner */
   double side;              /* root cube side */
+  int64_t n_nearquad_pairs; /* close panel pairs with exact integrals (0 unless near_quad > 0) */
 } bemfmm_tree_info;
 
 /* Build the octree and interaction lists for a mesh and a set of charges

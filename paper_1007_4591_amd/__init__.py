@@ -41,7 +41,8 @@ class NotConverged(BemfmmError):
 
 class _Params(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("ncrit", ctypes.c_int), ("theta", ctypes.c_double),
-                ("mac", ctypes.c_int), ("eps_in", ctypes.c_double), ("eps_out", ctypes.c_double)]
+                ("mac", ctypes.c_int), ("eps_in", ctypes.c_double), ("eps_out", ctypes.c_double),
+                ("near_quad", ctypes.c_double)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -54,7 +55,8 @@ class _TreeInfo(ctypes.Structure):
                 ("n_cells", ctypes.c_int64), ("n_leaves", ctypes.c_int64), ("n_near_pairs", ctypes.c_int64),
                 ("n_far_pairs", ctypes.c_int64), ("n_m2l_panel_pairs", ctypes.c_int64),
                 ("n_offsets", ctypes.c_int64),
-                ("p2p_pairs_panels", ctypes.c_int64), ("lo", ctypes.c_double * 3), ("side", ctypes.c_double)]
+                ("p2p_pairs_panels", ctypes.c_int64), ("lo", ctypes.c_double * 3), ("side", ctypes.c_double),
+                ("n_nearquad_pairs", ctypes.c_int64)]
 
 
 @dataclass
@@ -66,10 +68,11 @@ class Params:
     mac: int = MAC_THETA
     eps_in: float = 4.0
     eps_out: float = 80.0
+    near_quad: float = 0.0
 
     def _c(self):
         return _Params(int(self.p), int(self.ncrit), float(self.theta), int(self.mac), float(self.eps_in),
-                       float(self.eps_out))
+                       float(self.eps_out), float(self.near_quad))
 
 
 @dataclass

@@ -93,6 +93,7 @@ int bemfmm_build_tree(const double *verts, int64_t nv, const int32_t *tris, int6
     need(P.mac == BEMFMM_MAC_ADJACENT || (P.theta >= 0.3 && P.theta <= 1.0), "theta outside [0.3, 1]");
     need(P.eps_in > 0 && P.eps_out > 0 && std::isfinite(P.eps_in) && std::isfinite(P.eps_out),
          "permittivities must be positive");
+    need(std::isfinite(P.near_quad) && P.near_quad >= 0.0 && P.near_quad <= 16.0, "near_quad outside [0, 16]");
     Tree *T = new Tree();
     try {
       HIP_OK(hipGetDevice(&T->device));
@@ -146,6 +147,7 @@ int bemfmm_tree_get_info(const bemfmm_tree *tree, bemfmm_tree_info *info) {
     I.n_leaves = T->ncell[T->L];
     I.n_near_pairs = T->n_near_leaf;
     I.n_far_pairs = T->nfar;
+    I.n_nearquad_pairs = T->n_nq;
     I.n_m2l_panel_pairs = T->m2l[0].n;
     I.n_offsets = T->tab ? T->tab->noff() : 0;
     I.p2p_pairs_panels = T->p2p_pairs_pp;

@@ -244,6 +244,15 @@ struct Tree {
     int64_t max_cells = 0;
   } l2lw;
 
+  // near quadrature (params.near_quad = nu > 0): per sorted panel, the close
+  // source panels (|c_t - c_j| < nu rho_j) as a CSR of caller indices, with
+  // 4 pi (K'_tj exact - K'_tj one-point) in FP64, for A; and the transposed
+  // lists for A^T (K'_it; the product divides by the area of t), added to the
+  // near field
+  DBuf<int32_t> nq_ptr, nq_idx, nqT_ptr, nqT_idx;
+  DBuf<double> nq_coef, nqT_coef;
+  int64_t n_nq = 0, n_nqT = 0;
+
   // P2P work decomposition: (leaf, first sorted index, count, lane groups)
   // per chunk of at most 64 targets of one leaf
   DBuf<int4> chunk_p, chunk_q;
@@ -290,6 +299,7 @@ Tree *check_tree(const bemfmm_tree *t);
 // tree_build.hip
 void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
                 const double *qpos, int64_t nq, hipStream_t s);
+void build_nearquad(Tree &T, const double *verts, const int32_t *tris, hipStream_t s);
 void set_charges(Tree &T, const double *qpos, hipStream_t s);
 void set_charges_noalloc(Tree &T, const double *qpos, hipStream_t s);
 int64_t noalloc_max_charges();

@@ -973,6 +973,23 @@ __device__ __forceinline__ void pair_accumulate(const typename V4<R>::T &s4, con
   pair_eval_r2<R, SRC, OUT>(s4, m4, dx, dy, dz, r2, skip, lp, lx, ly, lz);
 }
 
+// Near quadrature: near_out[t] += sum over the close pairs of t, in list
+// order, of coef * x[caller index] (FP64; 4 pi times the exact-minus-point
+// difference of K' or of K'^T, see the tree's nq lists).  For A^T the sum is
+// divided by the target's area as the product stores it (the combine
+// multiplies the near field by that same area).
+template <class R>
+__global__ void k_nq_apply(int64_t n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                           const double *__restrict__ coef, const double *__restrict__ x,
+                           const typename V4<R>::T *__restrict__ tgt_pos, double *__restrict__ near_out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double acc = 0.0;
+  for (int k = ptr[t]; k < ptr[t + 1]; ++k) acc += coef[k] * x[idx[k]];
+  if (tgt_pos) acc /= (double)tgt_pos[t].w;
+  near_out[t] += acc;
+}
+
 struct P2PArgs {
   int p, ps;
   const int4 *chunks;        // (leaf, first target, count, lane groups) per chunk
@@ -1542,6 +1559,13 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
       }
 #undef P2P_CALL
       LAUNCH_OK();
+      if (T.n_nq > 0 && (rq.op == BEMFMM_OP_A || rq.op == BEMFMM_OP_AT)) {
+        const bool tr = rq.op == BEMFMM_OP_AT;
+        k_nq_apply<R><<<cdiv(T.N, 256), 256, 0, ss>>>(
+            T.N, tr ? T.nqT_ptr.p : T.nq_ptr.p, tr ? T.nqT_idx.p : T.nq_idx.p, tr ? T.nqT_coef.p : T.nq_coef.p,
+            tr ? rq.wdip : rq.wmono, tr ? reinterpret_cast<const R4 *>(a.tgt_pos) : nullptr, B.near_out.p);
+        LAUNCH_OK();
+      }
       prof_end(T, ST_P2P, ss);
       HIP_OK(hipEventRecord(T.ev_join, ss));
     }

@@ -1298,10 +1298,161 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     if (!cq.empty())
       HIP_OK(hipMemcpyAsync(T.chunk_q.p, cq.data(), cq.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   }
+  if (T.prm.near_quad > 0.0) build_nearquad(T, verts, tris, s);
   HIP_OK(hipStreamSynchronize(s));
 }
 
 namespace {
+
+// ----------------------------------------------------- near quadrature
+// (Section 2.1, discretisation paragraph: for flat panels the integrals can
+// be taken analytically.)  For a flat triangle T (vertices counter-clockwise
+// about its unit normal n) and a point r off its edges,
+//   grad_r of the integral over T of 1/|r - r'| dA' = - sum_e f_e m_e - W n,
+// with, per edge e from a to b: t = (b - a)/|b - a|, m = t x n (in-plane,
+// outward), f_e = asinh(s_b/d) - asinh(s_a/d) the integral of 1/|r - r'|
+// along the edge (s = (vertex - r).t, d the distance of r to the edge line),
+// and W the solid angle of T at r (Van Oosterom and Strackee's closed form),
+// positive on the side n points to and 0 in the plane of T.
+__device__ void tri_grad_exact(const double *__restrict__ verts, const int32_t *__restrict__ tri, const double r[3],
+                               double g[3]) {
+  double v[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int d = 0; d < 3; ++d) v[k][d] = verts[3 * (int64_t)tri[k] + d];
+  const double e1[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
+  const double e2[3] = {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]};
+  double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  const double nl = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  for (int d = 0; d < 3; ++d) n[d] /= nl;
+  g[0] = g[1] = g[2] = 0.0;
+  for (int e = 0; e < 3; ++e) {
+    const double *a = v[e], *b = v[(e + 1) % 3];
+    double t[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double tl = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    for (int d = 0; d < 3; ++d) t[d] /= tl;
+    const double m[3] = {t[1] * n[2] - t[2] * n[1], t[2] * n[0] - t[0] * n[2], t[0] * n[1] - t[1] * n[0]};
+    const double ar[3] = {a[0] - r[0], a[1] - r[1], a[2] - r[2]};
+    const double br[3] = {b[0] - r[0], b[1] - r[1], b[2] - r[2]};
+    const double sa = ar[0] * t[0] + ar[1] * t[1] + ar[2] * t[2];
+    const double sb = br[0] * t[0] + br[1] * t[1] + br[2] * t[2];
+    const double d2 = fmax(ar[0] * ar[0] + ar[1] * ar[1] + ar[2] * ar[2] - sa * sa, 0.0);
+    double f;
+    if (d2 > 1e-28 * fmax(sa * sa, sb * sb)) {
+      const double d = sqrt(d2);
+      f = asinh(sb / d) - asinh(sa / d);
+    } else {  // on the edge's line, outside the segment
+      f = copysign(log(fabs(sb) / fabs(sa)), sb);
+    }
+    for (int d = 0; d < 3; ++d) g[d] -= f * m[d];
+  }
+  double R[3][3], l[3];
+  for (int k = 0; k < 3; ++k) {
+    for (int d = 0; d < 3; ++d) R[k][d] = v[k][d] - r[d];
+    l[k] = sqrt(R[k][0] * R[k][0] + R[k][1] * R[k][1] + R[k][2] * R[k][2]);
+  }
+  const double c23[3] = {R[1][1] * R[2][2] - R[1][2] * R[2][1], R[1][2] * R[2][0] - R[1][0] * R[2][2],
+                         R[1][0] * R[2][1] - R[1][1] * R[2][0]};
+  // the triple product of v_k - r is negative on the side n points to (the
+  // counter-clockwise vertices turn clockwise seen from there)
+  const double num = -(R[0][0] * c23[0] + R[0][1] * c23[1] + R[0][2] * c23[2]);
+  auto dot3 = [](const double *x, const double *y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
+  const double den = l[0] * l[1] * l[2] + dot3(R[0], R[1]) * l[2] + dot3(R[0], R[2]) * l[1] + dot3(R[1], R[2]) * l[0];
+  const double W = (fabs(num) <= 1e-15 * l[0] * l[1] * l[2]) ? 0.0 : 2.0 * atan2(num, den);
+  for (int d = 0; d < 3; ++d) g[d] -= W * n[d];
+}
+
+// sorted-order centroid and circumradius (largest centroid-vertex distance)
+__global__ void k_nq_points(const int32_t *__restrict__ perm, int64_t N, const double *__restrict__ c,
+                            const double *__restrict__ verts, const int32_t *__restrict__ tris,
+                            double4 *__restrict__ cr, double *__restrict__ bmax) {
+  __shared__ double sh[256];
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double rho = 0.0;
+  if (i < N) {
+    const int64_t u = perm[i];
+    const double X = c[3 * u], Y = c[3 * u + 1], Z = c[3 * u + 2];
+    for (int k = 0; k < 3; ++k) {
+      const int64_t vk = tris[3 * u + k];
+      const double dx = verts[3 * vk] - X, dy = verts[3 * vk + 1] - Y, dz = verts[3 * vk + 2] - Z;
+      rho = fmax(rho, sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    cr[i] = make_double4(X, Y, Z, rho);
+  }
+  sh[threadIdx.x] = rho;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bmax[blockIdx.x] = sh[0];
+}
+
+// Close panel pairs of every sorted target panel, over its near leaves in
+// list order and the sources of each leaf in sorted order.  TRANSPOSE = 0
+// (A): the pairs (t, j) with |c_t - c_j| < nu rho_j, j != t; each stores the
+// source's caller index and 4 pi (K'_tj exact - K'_tj one-point).
+// TRANSPOSE = 1 (A^T): the pairs (i, t) with |c_i - c_t| < nu rho_t, i != t;
+// each stores i's caller index and the same difference for K'_it (the
+// product divides by the area of t).  FILL = 0 only counts.
+template <int TRANSPOSE, int FILL>
+__global__ void k_nq_pairs(int64_t N, const double4 *__restrict__ cr, const int32_t *__restrict__ pleaf,
+                           const int4 *__restrict__ leaf_range, const int32_t *__restrict__ leaf_xyz,
+                           const int32_t *__restrict__ near_ptr, const int32_t *__restrict__ near_idx, double lox,
+                           double loy, double loz, double sL, double nu, double reach,
+                           const int32_t *__restrict__ perm, const double *__restrict__ nrm,
+                           const double *__restrict__ area, const double *__restrict__ verts,
+                           const int32_t *__restrict__ tris, int32_t *__restrict__ cnt,
+                           const int32_t *__restrict__ ptr, int32_t *__restrict__ idx, double *__restrict__ coef) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const double4 ct = cr[t];
+  const int leaf = pleaf[t];
+  int32_t k = FILL ? ptr[t] : 0;
+  const int64_t ut = perm[t];
+  for (int e = near_ptr[leaf]; e < near_ptr[leaf + 1]; ++e) {
+    const int sl = near_idx[e];
+    // skip a leaf whose box lies farther than the largest radius
+    double X, Y, Z;
+    cell_centre(leaf_xyz[sl], lox, loy, loz, sL, X, Y, Z);
+    const double gx = fmax(fabs(ct.x - X) - 0.5 * sL, 0.0), gy = fmax(fabs(ct.y - Y) - 0.5 * sL, 0.0),
+                 gz = fmax(fabs(ct.z - Z) - 0.5 * sL, 0.0);
+    if (gx * gx + gy * gy + gz * gz >= reach * reach) continue;
+    const int4 rg = leaf_range[sl];
+    for (int j = rg.x; j < rg.y; ++j) {
+      if (j == t) continue;
+      const double4 cj = cr[j];
+      const double dx = ct.x - cj.x, dy = ct.y - cj.y, dz = ct.z - cj.z;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double lim = nu * (TRANSPOSE ? ct.w : cj.w);
+      if (!(r2 < lim * lim)) continue;
+      if (FILL) {
+        const int64_t uj = perm[j];
+        // pair (target i, source panel s) of K'
+        const int64_t ui = TRANSPOSE ? uj : ut, us = TRANSPOSE ? ut : uj;
+        const double ri[3] = {TRANSPOSE ? cj.x : ct.x, TRANSPOSE ? cj.y : ct.y, TRANSPOSE ? cj.z : ct.z};
+        double g[3];
+        tri_grad_exact(verts, tris + 3 * us, ri, g);
+        const double ni[3] = {nrm[3 * ui], nrm[3 * ui + 1], nrm[3 * ui + 2]};
+        // 4 pi K' exact = n_i . g;  4 pi K' one-point = -a_s n_i . (c_i - c_s) / r^3
+        const double sgn = TRANSPOSE ? -1.0 : 1.0;  // c_i - c_s = sgn (c_t - c_j)
+        const double ndot = sgn * (ni[0] * dx + ni[1] * dy + ni[2] * dz);
+        const double inv_r = 1.0 / sqrt(r2);
+        const double d4 = (ni[0] * g[0] + ni[1] * g[1] + ni[2] * g[2]) + area[us] * ndot * inv_r * inv_r * inv_r;
+        idx[k] = (int32_t)uj;
+        coef[k] = d4;
+      }
+      ++k;
+    }
+  }
+  if (!FILL) cnt[t] = k;
+}
+
+__global__ void k_sum_i32_to_u64(const int32_t *__restrict__ v, int64_t n, unsigned long long *__restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long x = (i < n) ? (unsigned long long)v[i] : 0ull;
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+  if ((threadIdx.x & 63) == 0 && x) atomicAdd(out, x);
+}
 
 __global__ void k_zero_i32(int *p) { *p = 0; }
 
@@ -1333,6 +1484,88 @@ unsigned char *scratch_ptr() {
 }
 
 }  // namespace
+
+// Smallest gap between two leaf boxes that are not in each other's near
+// list, in leaf sides: far pairs are M2L offsets at the leaf level or pairs
+// whose ancestors were far, whose gap in leaf sides is larger still.
+static double far_gap_leaf_sides(const Tables &tb) {
+  double g = 1e300;
+  for (int c = 0; c < tb.noff(); ++c) {
+    double s2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double a = std::max(std::abs(tb.offsets[3 * c + d]) - 1, 0);
+      s2 += a * a;
+    }
+    g = std::min(g, std::sqrt(s2));
+  }
+  return g;
+}
+
+void build_nearquad(Tree &T, const double *verts, const int32_t *tris, hipStream_t s) {
+  const int TB = 256;
+  const int64_t N = T.N;
+  const int L = T.L;
+  const double nu = T.prm.near_quad;
+  const double sL = T.side / double(1 << L);
+  DBuf<double4> cr;
+  cr.alloc(N);
+  const int nb = cdiv(N, TB);
+  DBuf<double> bmax;
+  bmax.alloc(nb);
+  k_nq_points<<<nb, TB, 0, s>>>(T.pperm.p, N, T.c.p, verts, tris, cr.p, bmax.p);
+  LAUNCH_OK();
+  std::vector<double> hb(nb);
+  HIP_OK(hipMemcpyAsync(hb.data(), bmax.p, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const double rho_max = *std::max_element(hb.begin(), hb.end());
+  const double reach = nu * rho_max;
+  // every close pair must lie in the near field, where the correction is
+  // applied to the direct sum
+  const double gap = (L >= 2 && T.tab) ? far_gap_leaf_sides(*T.tab) * sL : 1e300;
+  if (!(reach < gap))
+    BF_THROW(BEMFMM_EINVAL, "near_quad radius (" + std::to_string(reach) + ") reaches beyond the near field (" +
+                                std::to_string(gap) + "): lower near_quad or raise ncrit");
+  const int4 *lr = T.crange.p + T.coff[L];
+  const int32_t *lx = T.cxyz.p + T.coff[L];
+  const int32_t *np_ = T.near_ptr.p + T.near_ptr_off[L];
+  const int32_t *ni_ = T.near_idx.p + T.near_off[L];
+  for (int tr = 0; tr < 2; ++tr) {
+    DBuf<int32_t> &ptr = tr ? T.nqT_ptr : T.nq_ptr;
+    DBuf<int32_t> &idx = tr ? T.nqT_idx : T.nq_idx;
+    DBuf<double> &coef = tr ? T.nqT_coef : T.nq_coef;
+    DBuf<int32_t> cnt;
+    cnt.alloc(N);
+    ptr.alloc(N + 1);
+    auto launch = [&](auto tpl_tr, auto tpl_fill) {
+      constexpr int TR = decltype(tpl_tr)::value, FILL = decltype(tpl_fill)::value;
+      k_nq_pairs<TR, FILL><<<nb, TB, 0, s>>>(N, cr.p, T.pleaf.p, lr, lx, np_, ni_, T.lo[0], T.lo[1], T.lo[2], sL, nu,
+                                             reach, T.pperm.p, T.nrm.p, T.area.p, verts, tris, cnt.p, ptr.p, idx.p,
+                                             coef.p);
+      LAUNCH_OK();
+    };
+    if (tr) launch(std::integral_constant<int, 1>(), std::integral_constant<int, 0>());
+    else launch(std::integral_constant<int, 0>(), std::integral_constant<int, 0>());
+    DBuf<unsigned long long> tot;
+    tot.alloc(1);
+    tot.zero(s);
+    k_sum_i32_to_u64<<<nb, TB, 0, s>>>(cnt.p, N, tot.p);
+    LAUNCH_OK();
+    unsigned long long h = 0;
+    HIP_OK(hipMemcpyAsync(&h, tot.p, 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (h >= (1ull << 31)) BF_THROW(BEMFMM_EINVAL, "near_quad: more than 2^31 close panel pairs; lower near_quad");
+    exclusive_scan_i32(cnt.p, ptr.p, N, s, nullptr);
+    const int32_t total = (int32_t)h;
+    HIP_OK(hipMemcpyAsync(ptr.p + N, &total, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    idx.alloc(std::max<int64_t>(h, 1));
+    coef.alloc(std::max<int64_t>(h, 1));
+    if (tr) launch(std::integral_constant<int, 1>(), std::integral_constant<int, 1>());
+    else launch(std::integral_constant<int, 0>(), std::integral_constant<int, 1>());
+    if (tr) T.n_nqT = (int64_t)h;
+    else T.n_nq = (int64_t)h;
+  }
+  HIP_OK(hipStreamSynchronize(s));
+}
 
 int64_t noalloc_max_charges() {
   // error word (256 B), then Q float4 and Q double4, each block 256-B aligned
