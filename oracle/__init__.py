@@ -18,6 +18,9 @@ Contents
 * ``panel_integrals`` -- exact integrals of the Green's function and its
                        gradient over flat triangles, and the near-quadrature
                        K' (exact integrals for close panel pairs).
+* ``lpb``           -- dense linearised Poisson-Boltzmann BEM (screened
+                       solvent): the second-kind system for the surface
+                       potential and its normal derivative, energies.
 """
 from .dense import *  # noqa: F401,F403
-from . import closed_forms, tree, harmonics, panel_integrals  # noqa: F401
+from . import closed_forms, tree, harmonics, panel_integrals, lpb  # noqa: F401

@@ -24,6 +24,17 @@ permittivity eps_out, point charges q_i at r_i with |r_i| < a.
       c_n = -s (n+1) / (eps_in (2n+1)).
   For n = 0, c_0 = c_0^CFA: the CFA is exact for a centred charge, whose
   normal field is uniform on the sphere.
+* Linearised Poisson-Boltzmann solvent (Section 2.1: the screened equation
+  lap phi = kappa^2 phi outside, no ion-exclusion layer): the same series
+  with the exterior solution k_n(kappa r) P_n instead of r^(-n-1) P_n.
+  Matching potential and displacement at r = a for each Legendre term gives
+      c_n = ((n+1) eps_in + eps_out l_n) / (eps_in (n eps_in - eps_out l_n)),
+      l_n = x k_n'(x) / k_n(x),  x = kappa a,
+  with k_n the modified spherical Bessel function of the second kind
+  (l_n from the ratio recurrence in _lpb_lambda; the tests check it against
+  scipy.special.spherical_kn).  kappa = 0 gives l_n = -(n+1), the Kirkwood
+  coefficients above; n = 0 gives the screened Born ion,
+      dG = (K q^2 / 2a) (1 / (eps_out (1 + kappa a)) - 1/eps_in).
 """
 from __future__ import annotations
 
@@ -91,3 +102,36 @@ def sphere_energy_grad_q(pos, q, a, eps_in, eps_out, kind="exact", nmax=60) -> n
     q = np.asarray(q, dtype=np.float64)
     M = _series_matrix(pos, a, nmax, _coeffs(kind, nmax, eps_in, eps_out))
     return K_COULOMB * (M @ q)
+
+
+def born_screened(q: float, R: float, eps_in: float, eps_out: float, kappa: float) -> float:
+    return (K_COULOMB * q * q / (2.0 * R)) * (1.0 / (eps_out * (1.0 + kappa * R)) - 1.0 / eps_in)
+
+
+def _lpb_lambda(nmax: int, x: float) -> np.ndarray:
+    """l_n = x k_n'(x) / k_n(x) = n - x k_{n+1}(x)/k_n(x), with the ratio
+    r_n = k_{n+1}/k_n from r_0 = 1 + 1/x and the three-term recurrence
+    k_{n+1} = k_{n-1} + (2n+1)/x k_n, i.e. r_n = 1/r_{n-1} + (2n+1)/x (no
+    overflow at small x, where k_n itself does)."""
+    n = np.arange(nmax + 1, dtype=np.float64)
+    if x == 0.0:
+        return -(n + 1)
+    r = np.zeros(nmax + 1)
+    r[0] = 1.0 + 1.0 / x
+    for k in range(1, nmax + 1):
+        r[k] = 1.0 / r[k - 1] + (2 * k + 1) / x
+    return n - x * r
+
+
+def _coeffs_lpb(nmax: int, eps_in: float, eps_out: float, kappa: float, a: float) -> np.ndarray:
+    n = np.arange(nmax + 1, dtype=np.float64)
+    lam = _lpb_lambda(nmax, kappa * a)
+    return ((n + 1) * eps_in + eps_out * lam) / (eps_in * (n * eps_in - eps_out * lam))
+
+
+def sphere_energy_lpb(pos, q, a, eps_in, eps_out, kappa, nmax=60) -> float:
+    """Solvation energy of charges inside a sphere in a screened (linearised
+    Poisson-Boltzmann) solvent with inverse Debye length kappa (1/A)."""
+    q = np.asarray(q, dtype=np.float64)
+    M = _series_matrix(pos, a, nmax, _coeffs_lpb(nmax, eps_in, eps_out, kappa, a))
+    return 0.5 * K_COULOMB * float(q @ M @ q)
