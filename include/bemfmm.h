@@ -259,6 +259,36 @@ int bemfmm_binding_energy(bemfmm_tree *complex_tree, const double *q_complex, be
                           void *stream);
 
 /* Thread-local message for the last failure on this thread ("" if none). */
+/* ------------------------------------------------------------------------
+ * Linearised Poisson-Boltzmann solvent (Section 2.1: the screened equation
+ * lap phi = kappa^2 phi outside the molecule, named there and in Section 5
+ * as the method's next extension).  The paper gives no integral equation;
+ * the one solved here is the second-kind pair for the surface potential
+ * u = phi and its interior normal derivative v = d phi/dn (n outward), with
+ * eps = eps_out/eps_in, G0 = 1/(4 pi r), Gk = exp(-kappa r)/(4 pi r):
+ *   (1+eps)/2 u + (K0 - eps Kk) u - (V0 - Vk) v = S
+ *   (1+1/eps)/2 v - (K0' - Kk'/eps) v + (D0 - Dk) u = dS/dn
+ * (V single layer, K double layer, K' its adjoint, D the normal derivative of
+ * the double layer; S = sum_k q_k G0(., r_k)/eps_in), collocated at the
+ * centroids with one point per panel; the self terms of V0 - Vk and D0 - Dk
+ * are exact integrals over the flat panel, the others vanish.  The far field
+ * of Gk is a screened-kernel FMM on the same tree (per-level operators built
+ * on the GPU at the first call with a new kappa); everything runs in FP64.
+ * uv and y are [2N] = (u, v) in caller panel order; kappa > 0 in 1/A with
+ * kappa * (root cube side) <= 400 (EINVAL otherwise).
+ *
+ * y = M uv (the operator above). */
+int bemfmm_lpb_matvec(bemfmm_tree *tree, double kappa, const double *uv, double *y, void *stream);
+
+/* Solve M uv = [S; dS/dn] by GMRES(restart) from 0 to the relative residual
+ * tol (explicit, in info); ENOCONV at maxit with uv the last iterate. */
+int bemfmm_lpb_solve(bemfmm_tree *tree, const double *q, double kappa, double *uv, double tol, int maxit,
+                     int restart, bemfmm_solve_info *info, void *stream);
+
+/* Solvation energy of a solution uv: dG = 2 pi K sum_k q_k phi_reac(r_k),
+ * phi_reac = SL0(a v) - DL0(a u) the reaction potential (kcal/mol). */
+int bemfmm_lpb_energy(bemfmm_tree *tree, const double *q, const double *uv, double *dG_host, void *stream);
+
 const char *bemfmm_last_error(void);
 
 /* Device memory of destroyed trees and of grown workspaces is kept by the

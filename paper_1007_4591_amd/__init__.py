@@ -121,11 +121,15 @@ def _load():
     lib.bemfmm_profile_select.argtypes = [P, I, I]
     lib.bemfmm_debug_record.argtypes = [P, I]
     lib.bemfmm_binding_energy.argtypes = [P, P, P, P, P, P, I, I, D, I, I, ctypes.POINTER(D), P]
+    lib.bemfmm_lpb_matvec.argtypes = [P, D, P, P, P]
+    lib.bemfmm_lpb_solve.argtypes = [P, P, D, P, D, I, I, ctypes.POINTER(_SolveInfo), P]
+    lib.bemfmm_lpb_energy.argtypes = [P, P, P, ctypes.POINTER(D), P]
     for name in ("bemfmm_build_tree", "bemfmm_set_charges", "bemfmm_set_charges_noalloc", "bemfmm_tree_destroy", "bemfmm_tree_get_info",
                  "bemfmm_fmm_matvec", "bemfmm_solve_bem", "bemfmm_bibee_energy", "bemfmm_solvation_energy",
                  "bemfmm_adjoint_grad", "bemfmm_tree_export", "bemfmm_debug_expansions", "bemfmm_debug_fields",
                  "bemfmm_profile", "bemfmm_profile_get", "bemfmm_release_cache", "bemfmm_profile_select",
-                 "bemfmm_debug_record", "bemfmm_binding_energy"):
+                 "bemfmm_debug_record", "bemfmm_binding_energy", "bemfmm_lpb_matvec", "bemfmm_lpb_solve",
+                 "bemfmm_lpb_energy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -273,6 +277,36 @@ def solve_bem(tree: Tree, q, tol=1e-6, maxit=200, restart=30, precision=FP32_REF
     return x, _info(si)
 
 
+def lpb_matvec(tree: Tree, kappa, uv, y=None, stream=None):
+    """bemfmm_lpb_matvec: y = M uv, the linearised Poisson-Boltzmann operator
+    on uv = (u, v) [2N]."""
+    d = _to_dev(uv, torch.float64)
+    if y is None:
+        y = torch.empty(2 * tree.n_panels, dtype=torch.float64, device=d.device)
+    _check(_load().bemfmm_lpb_matvec(tree.handle, float(kappa), _ptr(d), _ptr(y), _stream(stream)))
+    return y
+
+
+def lpb_solve(tree: Tree, q, kappa, tol=1e-8, maxit=300, restart=50, uv=None, stream=None):
+    """bemfmm_lpb_solve: uv = (u, v) of the screened-solvent system; returns (uv, SolveInfo)."""
+    qd = _to_dev(q, torch.float64)
+    if uv is None:
+        uv = torch.empty(2 * tree.n_panels, dtype=torch.float64, device=qd.device)
+    si = _SolveInfo()
+    _check(_load().bemfmm_lpb_solve(tree.handle, _ptr(qd), float(kappa), _ptr(uv), float(tol), int(maxit),
+                                    int(restart), ctypes.byref(si), _stream(stream)))
+    return uv, _info(si)
+
+
+def lpb_energy(tree: Tree, q, uv, stream=None) -> float:
+    """bemfmm_lpb_energy: solvation energy (kcal/mol) of a solution uv."""
+    qd = _to_dev(q, torch.float64)
+    d = _to_dev(uv, torch.float64)
+    out = ctypes.c_double()
+    _check(_load().bemfmm_lpb_energy(tree.handle, _ptr(qd), _ptr(d), ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
 def bibee_energy(tree: Tree, q, kind=BIBEE_CFA, precision=FP32, stream=None) -> float:
     qd = _to_dev(q, torch.float64)
     out = ctypes.c_double()
@@ -387,5 +421,5 @@ __all__ = [
     "MAC_THETA", "MAC_ADJACENT", "Params", "SolveInfo", "Tree", "BemfmmError", "NotConverged", "build_tree",
     "set_charges", "set_charges_noalloc", "tree_destroy", "fmm_matvec", "solve_bem", "bibee_energy", "solvation_energy", "adjoint_grad",
     "tree_export", "debug_expansions", "debug_fields", "profile", "profile_get", "library_path",
-    "release_cache", "profile_select",
+    "release_cache", "profile_select", "lpb_matvec", "lpb_solve", "lpb_energy",
 ]

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbemfmm.so")
-SOURCES = ["alloc.cpp", "tables.cpp", "tree_build.hip", "fmm.hip", "solve.hip", "capi.cpp"]
+SOURCES = ["alloc.cpp", "tables.cpp", "tree_build.hip", "fmm.hip", "solve.hip", "yukawa.hip", "capi.cpp"]
 ARCH = os.environ.get("BEMFMM_ARCH", "gfx950")
 
 

@@ -16,6 +16,7 @@ void set_error(const std::string &msg) { g_err = msg; }
 
 Tree::~Tree() {
   fmm_free(*this);
+  lpb_free(*this);
   if (ev_init) {
     for (auto &e : ev) (void)hipEventDestroy(e);
     (void)hipEventDestroy(ev_fork);
@@ -122,6 +123,42 @@ int bemfmm_set_charges_noalloc(bemfmm_tree *tree, const double *charge_pos, void
     DeviceScope dev_scope(*T);
     need(T->Q == 0 || charge_pos, "charge_pos is NULL");
     set_charges_noalloc(*T, charge_pos, (hipStream_t)stream);
+  });
+}
+
+static void need_kappa(const Tree &T, double kappa) {
+  need(std::isfinite(kappa) && kappa > 0.0, "kappa must be positive");
+  need(kappa * T.side <= 400.0, "kappa times the root cube side exceeds 400");
+}
+
+int bemfmm_lpb_matvec(bemfmm_tree *tree, double kappa, const double *uv, double *y, void *stream) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
+    need_kappa(*T, kappa);
+    need(uv && y, "uv/y are NULL");
+    lpb_matvec(*T, kappa, uv, y, (hipStream_t)stream);
+  });
+}
+
+int bemfmm_lpb_solve(bemfmm_tree *tree, const double *q, double kappa, double *uv, double tol, int maxit,
+                     int restart, bemfmm_solve_info *info, void *stream) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
+    need_kappa(*T, kappa);
+    need(uv != nullptr && (T->Q == 0 || q != nullptr), "q/uv are NULL");
+    need(tol > 0 && maxit >= 1, "tol must be > 0 and maxit >= 1");
+    lpb_solve(*T, q, kappa, uv, tol, maxit, restart, info, (hipStream_t)stream);
+  });
+}
+
+int bemfmm_lpb_energy(bemfmm_tree *tree, const double *q, const double *uv, double *dG_host, void *stream) {
+  return guard([&] {
+    Tree *T = check_tree(tree);
+    DeviceScope dev_scope(*T);
+    need(dG_host != nullptr && uv != nullptr && (T->Q == 0 || q != nullptr), "q/uv/dG are NULL");
+    *dG_host = lpb_energy(*T, q, uv, (hipStream_t)stream);
   });
 }
 

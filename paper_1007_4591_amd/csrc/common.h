@@ -16,6 +16,7 @@
 #include <stdint.h>
 
 #include <cstddef>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -154,6 +155,7 @@ bool mac_far_host(int ox, int oy, int oz, double theta, int mac);
 // ---------------------------------------------------------------- tree
 
 struct PrecBufs;  // per-precision FMM buffers (fmm.hip)
+struct LpbState;  // screened-kernel state of a tree (yukawa.hip)
 
 struct Tree {
   int magic = 0x5eedbe11;
@@ -170,6 +172,7 @@ struct Tree {
 
   // user-order geometry (FP64)
   DBuf<double> c, nrm, area;  // 3N, 3N, N
+  DBuf<double> pverts;        // 9N: the three vertices of each panel (caller order)
   DBuf<double> qpos;          // 3Q user-order charge positions (current)
 
   // Morton order
@@ -259,6 +262,7 @@ struct Tree {
   int64_t nchunk_p = 0, nchunk_q = 0;
 
   PrecBufs *pb32 = nullptr, *pb64 = nullptr;
+  LpbState *lpb = nullptr;  // screened-kernel tables, lists and buffers (yukawa.hip)
 
   // persistent FP64 work vectors of the solvers, by purpose (grow only)
   std::map<std::string, std::unique_ptr<DBuf<double>>> work;
@@ -328,6 +332,7 @@ struct FmmRequest {
   double *y;            // OUT_POT/NGRAD: [n_targets]; OUT_POTGRAD: [n_targets*4] (pot, gx, gy, gz)
   bool accumulate;      // y += instead of y =
   int op = -1;          // BEMFMM_OP_* this request implements (-1: another product), for stage timing
+  bool far_only = false;  // skip the near field (the caller adds its own direct sums)
 };
 
 void fmm_apply(Tree &T, int precision, const FmmRequest &rq, hipStream_t s);
@@ -347,6 +352,28 @@ double molecule_energy(Tree &T, const double *q, int method, int precision, doub
 void adjoint(Tree &T, const double *q, const double *x, double tol, int maxit, int restart, int precision,
              double *dq, double *dpos, bemfmm_solve_info *info, hipStream_t s);
 double dot_d(Tree &T, const double *a, const double *b, int64_t n, hipStream_t s);
+// GMRES(restart) from x = 0 on any operator of vectors of length n; returns the iterations
+int gmres_apply(Tree &T, const std::function<void(const double *, double *)> &A, int64_t n, const double *b,
+                double *x, double tol, int maxit, int restart, hipStream_t s);
+
+// FP64 building blocks of the FMM shared with the screened-kernel (Yukawa)
+// far field of yukawa.hip: the batched per-level MFMA product (M2M when m2m,
+// else L2L) with a given octant table, the parents' sums of M2M rows, the
+// offset-grouped MFMA M2L over a work list with a given operator table, and
+// the downward pass of one level without leaf evaluation coefficients.
+void level_product64(Tree &T, int l, const int32_t *src, const double *table, const double *in, double *out,
+                     bool m2m, hipStream_t s);
+void m2m_sum64(Tree &T, int l, const double *rows, double *M, hipStream_t s);
+void m2l_tiles64(const Tree::M2LList &ML, int ps, const double *table, const double *M, double *out, hipStream_t s);
+void downward64(Tree &T, int l, const double *l2l_rows, const int32_t *kptr, const double *m2l_rows, double *Lx,
+                hipStream_t s);
+
+// linearised Poisson-Boltzmann (yukawa.hip)
+void lpb_free(Tree &T);
+void lpb_matvec(Tree &T, double kappa, const double *uv, double *y, hipStream_t s);
+void lpb_solve(Tree &T, const double *q, double kappa, double *uv, double tol, int maxit, int restart,
+               bemfmm_solve_info *info, hipStream_t s);
+double lpb_energy(Tree &T, const double *q, const double *uv, hipStream_t s);
 
 // profiling helpers (fmm.hip)
 enum Stage { ST_P2M = 0, ST_M2M = 1, ST_M2L = 2, ST_L2L = 3, ST_P2P = 4, ST_OTHER = 5, ST_L2P = 6 };

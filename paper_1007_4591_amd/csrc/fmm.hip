@@ -1244,22 +1244,24 @@ __global__ void __launch_bounds__(64) k_l2p_combine(P2PArgs a) {
   const int64_t u = a.tperm[ti];
   double res[4], near_v, far_v;
   int nres = 1;
+  // near_out is NULL for a far-field-only product
+  const double *no = a.near_out;
   if (OUT == OUT_POT) {
-    near_v = a.near_out[ti];
+    near_v = no ? no[ti] : 0.0;
     far_v = (double)fp;
     res[0] = near_v + far_v;
   } else if (OUT == OUT_NGRAD) {
     const R4 nn = reinterpret_cast<const R4 *>(a.tgt_nrm)[ti];
-    near_v = a.near_out[ti];
+    near_v = no ? no[ti] : 0.0;
     far_v = (double)nn.x * fgx + (double)nn.y * fgy + (double)nn.z * fgz;
     res[0] = near_v + far_v;
   } else {
-    near_v = a.near_out[4 * (size_t)ti];
+    near_v = no ? no[4 * (size_t)ti] : 0.0;
     far_v = (double)fp;
     res[0] = near_v + far_v;
-    res[1] = a.near_out[4 * (size_t)ti + 1] + (double)fgx;
-    res[2] = a.near_out[4 * (size_t)ti + 2] + (double)fgy;
-    res[3] = a.near_out[4 * (size_t)ti + 3] + (double)fgz;
+    res[1] = (no ? no[4 * (size_t)ti + 1] : 0.0) + (double)fgx;
+    res[2] = (no ? no[4 * (size_t)ti + 2] : 0.0) + (double)fgy;
+    res[3] = (no ? no[4 * (size_t)ti + 3] : 0.0) + (double)fgz;
     nres = 4;
   }
   if (a.dbg_near) {
@@ -1520,7 +1522,7 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   a.dbg_near = T.debug_record ? B.dbg_near.p : nullptr;
   a.dbg_far = T.debug_record ? B.dbg_far.p : nullptr;
   B.dbg_valid = T.debug_record;
-  a.near_out = B.near_out.p;
+  a.near_out = rq.far_only ? nullptr : B.near_out.p;
   B.last_tgt = rq.tgt;
   // The near field runs on the second stream, forked from the caller's
   // stream at a point of the upward pass and joined before L2P.  It forks
@@ -1537,6 +1539,7 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   const bool big_m2l = T.m2l_persistent && ML.ntiles >= 32 * (int64_t)T.n_cu;
   const int fork_at = !far ? FORK_START : T.fork_at >= 0 ? T.fork_at : (big_m2l ? FORK_AFTER_M2M : FORK_AFTER_P2M);
   auto fork_near = [&]() {
+    if (rq.far_only) return;
     HIP_OK(hipEventRecord(T.ev_fork, s));
     if (nchunks > 0) {
       HIP_OK(hipStreamWaitEvent(ss, T.ev_fork, 0));
@@ -1657,7 +1660,7 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
 
   // far field + near field -> output, after the join
   if (nchunks > 0) {
-    HIP_OK(hipStreamWaitEvent(s, T.ev_join, 0));
+    if (!rq.far_only) HIP_OK(hipStreamWaitEvent(s, T.ev_join, 0));
     prof_begin(T, ST_L2P, s);
 #define L2P_CALL(Tg, O)                                                 \
   do {                                                                  \
@@ -1668,6 +1671,7 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   } while (0)
     if (!tgt_ch) {
       if (rq.out == OUT_NGRAD) L2P_CALL(TGT_PANEL, OUT_NGRAD);
+      else if (rq.out == OUT_POTGRAD) L2P_CALL(TGT_PANEL, OUT_POTGRAD);
       else L2P_CALL(TGT_PANEL, OUT_POT);
     } else {
       if (rq.out == OUT_POTGRAD) L2P_CALL(TGT_CHARGE, OUT_POTGRAD);
@@ -1705,6 +1709,55 @@ void fmm_apply(Tree &T, int precision, const FmmRequest &rq, hipStream_t s) {
     run_fmm<double>(T, B, rq, s);
   else
     run_fmm<float>(T, B, rq, s);
+}
+
+void level_product64(Tree &T, int l, const int32_t *src, const double *table, const double *in, double *out,
+                     bool m2m, hipStream_t s) {
+  if (m2m)
+    level_product<double, 2>(T, l, src, table, in, out, s);
+  else
+    level_product<double, 1>(T, l, src, table, in, out, s);
+}
+
+void m2m_sum64(Tree &T, int l, const double *rows, double *M, hipStream_t s) {
+  const int64_t CP = T.ncell[l - 1];
+  k_m2m_sum<double><<<cdiv(CP * T.ps, 256), 256, 0, s>>>(T.ps, T.coff[l - 1], CP, T.coff[l], T.cchild.p, rows, M);
+  LAUNCH_OK();
+}
+
+void m2l_tiles64(const Tree::M2LList &ML, int ps, const double *table, const double *M, double *out, hipStream_t s) {
+  if (ML.ntiles64 <= 0) return;
+  const dim3 grid((unsigned)ML.ntiles64);
+#define M2L64_CASE(nt)                                                                                      \
+  case nt:                                                                                                  \
+    k_m2l<double, nt, M2L_RT64, false, 0><<<grid, 256, 0, s>>>(ML.tile_group64.p, ML.tile_row64.p,         \
+                                                                ML.group_off.p, ML.group_end.p, ML.src.p,  \
+                                                                ML.dest.p, table, M, out);                 \
+    break;
+  switch (ps / 16) {
+    M2L64_CASE(1)
+    M2L64_CASE(2)
+    M2L64_CASE(3)
+    M2L64_CASE(4)
+    M2L64_CASE(5)
+    M2L64_CASE(6)
+    M2L64_CASE(7)
+    M2L64_CASE(8)
+    default:
+      BF_THROW(BEMFMM_EINVAL, "unsupported expansion order");
+  }
+#undef M2L64_CASE
+  LAUNCH_OK();
+}
+
+void downward64(Tree &T, int l, const double *l2l_rows, const int32_t *kptr, const double *m2l_rows, double *Lx,
+                hipStream_t s) {
+  const int ps = T.ps;
+  const int nthr = T.ncell[l] < 4 * T.n_cu * 8 ? 256 : 64;
+  const size_t shm = (size_t)(ps + nthr * VecT<double>::W) * sizeof(double);
+  k_downward<double><<<T.ncell[l], nthr, shm, s>>>(T.p, ps, T.coff[l], T.ncell[l], l > 2 ? 1 : 0, l2l_rows, kptr,
+                                                   m2l_rows, Lx, 0, 1.0, nullptr);
+  LAUNCH_OK();
 }
 
 void fmm_free(Tree &T) {

@@ -14,6 +14,8 @@
 #include <chrono>
 #include <cmath>
 
+#include <functional>
+
 #include "common.h"
 
 namespace bemfmm {
@@ -121,9 +123,9 @@ __global__ void k_adjoint_out(const double *__restrict__ pg, const double *__res
 struct Ws {
   double *partial = nullptr, *h = nullptr;
   size_t cap = 0;
-  Ws(Tree &T, size_t nvec, const char *tag) {
+  Ws(Tree &T, size_t nvec, const char *tag, int64_t nlen = 0) {
     cap = (size_t)std::max(1, std::min(512, (int)((T.N + 4 * 256 - 1) / (4 * 256)))) * std::max<size_t>(nvec, 1);
-    const int64_t nmax = std::max<int64_t>(T.N, T.Q);
+    const int64_t nmax = std::max<int64_t>(std::max<int64_t>(T.N, T.Q), nlen);
     cap = std::max(cap, (size_t)std::max(1, std::min(512, (int)((nmax + 1023) / 1024))) * std::max<size_t>(nvec, 1));
     partial = T.buf(std::string("wsp_") + tag, cap);
     h = T.buf(std::string("wsh_") + tag, 4);
@@ -156,13 +158,12 @@ struct GmresOut {
   double est = 0.0;  // Givens residual estimate relative to |b|
 };
 
-// GMRES(m) from x = 0 on the operator `op` at matvec precision `prec`:
-// stops when the Givens estimate |g_{k+1}| <= tol |b| or after maxit steps.
-GmresOut gmres(Tree &T, int op, int prec, const double *b, double *x, double tol, int maxit, int restart,
-               hipStream_t s) {
-  const int64_t n = T.N;
+// GMRES(m) from x = 0 on the operator A (vectors of length n): stops when
+// the Givens estimate |g_{k+1}| <= tol |b| or after maxit steps.
+GmresOut gmres_fn(Tree &T, const std::function<void(const double *, double *)> &A, int64_t n, const double *b,
+                  double *x, double tol, int maxit, int restart, hipStream_t s) {
   const int m = std::max(1, std::min(restart > 0 ? restart : 30, maxit > 0 ? maxit : 1));
-  Ws ws(T, m + 2, "gmres");
+  Ws ws(T, m + 2, "gmres", n);
   struct { double *p; } V{T.buf("gm_V", (size_t)(m + 1) * n)}, w{T.buf("gm_w", n)}, hd{T.buf("gm_hd", 2 * (m + 2))},
       yv{T.buf("gm_y", m + 1)}, r{T.buf("gm_r", n)}, ax{T.buf("gm_ax", n)};
   HIP_OK(hipMemsetAsync(x, 0, n * 8, s));
@@ -172,11 +173,11 @@ GmresOut gmres(Tree &T, int op, int prec, const double *b, double *x, double tol
   HIP_OK(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
   double beta = bnorm;
   const int TB = 256;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hh(m + 2), y(m);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hh(m + 2), y(m), h1(m + 1), h2(m + 2);
   bool first = true;
   while (out.iters < maxit) {
     if (!first) {
-      op_apply(T, op, prec, x, ax.p, s);
+      A(x, ax.p);
       k_sub<<<cdiv(n, TB), TB, 0, s>>>(r.p, b, ax.p, n);
       LAUNCH_OK();
       beta = std::sqrt(dot_host(ws, r.p, r.p, n, s));
@@ -191,7 +192,7 @@ GmresOut gmres(Tree &T, int op, int prec, const double *b, double *x, double tol
     int k = 0;
     for (; k < m && out.iters < maxit; ++k) {
       double *vk = V.p + (size_t)k * n, *vn = V.p + (size_t)(k + 1) * n;
-      op_apply(T, op, prec, vk, w.p, s);
+      A(vk, w.p);
       // classical Gram-Schmidt, twice
       dots(ws, V.p, n, k + 1, w.p, n, hd.p, 0, s);
       k_orth_update<<<cdiv(n, TB), TB, 0, s>>>(w.p, V.p, n, k + 1, hd.p, n);
@@ -200,7 +201,6 @@ GmresOut gmres(Tree &T, int op, int prec, const double *b, double *x, double tol
       k_orth_update<<<cdiv(n, TB), TB, 0, s>>>(w.p, V.p, n, k + 1, hd.p + (m + 2), n);
       LAUNCH_OK();
       dots(ws, w.p, n, 1, w.p, n, hd.p + (m + 2) + (k + 1), 0, s);
-      std::vector<double> h1(k + 1), h2(k + 2);
       HIP_OK(hipMemcpyAsync(h1.data(), hd.p, (k + 1) * 8, hipMemcpyDeviceToHost, s));
       HIP_OK(hipMemcpyAsync(h2.data(), hd.p + (m + 2), (k + 2) * 8, hipMemcpyDeviceToHost, s));
       HIP_OK(hipStreamSynchronize(s));
@@ -246,6 +246,12 @@ GmresOut gmres(Tree &T, int op, int prec, const double *b, double *x, double tol
   }
   HIP_OK(hipStreamSynchronize(s));
   return out;
+}
+
+GmresOut gmres(Tree &T, int op, int prec, const double *b, double *x, double tol, int maxit, int restart,
+               hipStream_t s) {
+  return gmres_fn(
+      T, [&](const double *v, double *w) { op_apply(T, op, prec, v, w, s); }, T.N, b, x, tol, maxit, restart, s);
 }
 
 double rel_residual64(Tree &T, int op, const double *b, const double *x, double bnorm, hipStream_t s) {
@@ -350,8 +356,13 @@ void op_apply(Tree &T, int op, int precision, const double *x, double *y, hipStr
 }
 
 double dot_d(Tree &T, const double *a, const double *b, int64_t n, hipStream_t s) {
-  Ws ws(T, 1, "dot");
+  Ws ws(T, 1, "dot", n);
   return dot_host(ws, a, b, n, s);
+}
+
+int gmres_apply(Tree &T, const std::function<void(const double *, double *)> &A, int64_t n, const double *b,
+                double *x, double tol, int maxit, int restart, hipStream_t s) {
+  return gmres_fn(T, A, n, b, x, tol, maxit, restart, s).iters;
 }
 
 void solve_bem(Tree &T, const double *q, double *x, double tol, int maxit, int restart, int precision,

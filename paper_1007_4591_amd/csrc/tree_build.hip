@@ -253,6 +253,17 @@ __global__ void k_geometry(const double *__restrict__ V, int64_t nv, const int32
   nrm[3 * i + 2] = m2 / len;
 }
 
+// the three vertices of each panel, caller order (9 doubles per panel)
+__global__ void k_panel_verts(const double *__restrict__ verts, const int32_t *__restrict__ tris, int64_t nt,
+                              double *__restrict__ pv) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  for (int k = 0; k < 3; ++k) {
+    const int64_t v = tris[3 * i + k];
+    for (int d = 0; d < 3; ++d) pv[9 * i + 3 * k + d] = verts[3 * v + d];
+  }
+}
+
 __global__ void k_check_points(const double *__restrict__ x, int64_t n, int *__restrict__ err) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -878,6 +889,9 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
   if (e & 1) BF_THROW(BEMFMM_EINVAL, "triangle vertex index out of range");
   if (e & 2) BF_THROW(BEMFMM_EINVAL, "degenerate (zero-area) or non-finite triangle");
   if (e & 4) BF_THROW(BEMFMM_EINVAL, "non-finite charge position");
+  T.pverts.alloc(9 * nt);
+  k_panel_verts<<<cdiv(nt, TB), TB, 0, s>>>(verts, tris, nt, T.pverts.p);
+  LAUNCH_OK();
 
   // bounding cube (exact min / max)
   {
