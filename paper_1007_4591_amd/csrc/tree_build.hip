@@ -584,38 +584,50 @@ __global__ void k_tile_list(const int32_t *__restrict__ gbeg, const int32_t *__r
 // keep a sorted M2L pair if its source cell has sources and its target cell
 // targets of the list's kinds (0 panels->panels, 1 charges->panels,
 // 2 panels->charges)
-__global__ void k_combo_flags(const int32_t *__restrict__ order, const int2 *__restrict__ ts,
-                              const int4 *__restrict__ crange, int64_t n, int combo, int32_t *__restrict__ flag) {
+// what each cell holds: bit 0 panels, bit 1 charges
+__global__ void k_cell_kinds(const int4 *__restrict__ crange, int64_t n, uint8_t *__restrict__ kind) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int4 r = crange[c];
+  kind[c] = (uint8_t)((r.y > r.x ? 1 : 0) | (r.w > r.z ? 2 : 0));
+}
+
+// a far pair is kept in list `combo` if its source cell has sources and its
+// target cell targets of the list's kinds (0 panels -> panels, 1 charges ->
+// panels, 2 panels -> charges)
+__device__ inline bool combo_keep(uint8_t kt, uint8_t ks, int combo) {
+  return combo == 0 ? ((ks & 1) && (kt & 1)) : (combo == 1 ? ((ks & 2) && (kt & 1)) : ((ks & 1) && (kt & 2)));
+}
+
+// the far pairs in offset order (one gather through the sort's permutation)
+__global__ void k_gather_pairs(const int32_t *__restrict__ order, const int2 *__restrict__ ts, int64_t n,
+                               int2 *__restrict__ ts_sorted) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) ts_sorted[i] = ts[order[i]];
+}
+
+// keep flags of one list, in the order of `ts` (offset order or pair order)
+__global__ void k_combo_flags(const int2 *__restrict__ ts, const uint8_t *__restrict__ kind, int64_t n, int combo,
+                              int32_t *__restrict__ flag) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int2 p = ts[order[i]];
-  const int4 rt = crange[p.x], rs = crange[p.y];
-  const bool tp = rt.y > rt.x, tq = rt.w > rt.z, sp = rs.y > rs.x, sq = rs.w > rs.z;
-  bool keep = combo == 0 ? (sp && tp) : (combo == 1 ? (sq && tp) : (sp && tq));
-  flag[i] = keep ? 1 : 0;
+  const int2 p = ts[i];
+  flag[i] = combo_keep(kind[p.x], kind[p.y], combo) ? 1 : 0;
 }
 
 __global__ void k_combo_compact(const int32_t *__restrict__ order, const uint32_t *__restrict__ key,
                                 const int32_t *__restrict__ flag, const int32_t *__restrict__ pos, int64_t n,
-                                const int2 *__restrict__ ts, const int32_t *__restrict__ pos_t,
+                                const int2 *__restrict__ ts_sorted, const int32_t *__restrict__ pos_t,
                                 int32_t *__restrict__ src_k, uint32_t *__restrict__ key_k,
                                 int32_t *__restrict__ dest_k) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (!flag[i]) return;
-  const int32_t pair = order[i];
-  src_k[pos[i]] = ts[pair].y;
+  src_k[pos[i]] = ts_sorted[i].y;
   key_k[pos[i]] = key[i];
-  dest_k[pos[i]] = pos_t[pair];
+  dest_k[pos[i]] = pos_t[order[i]];
 }
 
-// flag of each far pair in pair order (level, target, source) from the
-// flags in offset order
-__global__ void k_flag_by_pair(const int32_t *__restrict__ order, const int32_t *__restrict__ flag, int64_t n,
-                               int32_t *__restrict__ flag_t) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) flag_t[order[i]] = flag[i];
-}
 
 // first kept row of every cell (CSR over all cells, rows in pair order)
 __global__ void k_kept_ptr(const int32_t *__restrict__ far_ptr, const int32_t *__restrict__ pos_t, int64_t n1,
@@ -1177,21 +1189,30 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
     radix_sort_u32(key.p, order.p, nf, nbits, s);
     DBuf<int32_t> flag, pos, flag_t, pos_t;
     DBuf<uint32_t> ckeyc;
+    DBuf<uint8_t> kind;
+    DBuf<int2> ts_sorted;
     flag.alloc(nf);
     pos.alloc(nf);
     flag_t.alloc(nf + 1);
     pos_t.alloc(nf + 1);
     ckeyc.alloc(nf);
+    kind.alloc(T.ncell_tot);
+    ts_sorted.alloc(nf);
+    k_cell_kinds<<<cdiv(T.ncell_tot, TB), TB, 0, s>>>(T.crange.p, T.ncell_tot, kind.p);
+    LAUNCH_OK();
+    k_gather_pairs<<<cdiv(nf, TB), TB, 0, s>>>(order.p, T.far_ts.p, nf, ts_sorted.p);
+    LAUNCH_OK();
     const int64_t CT1 = T.ncell_tot + 1;
     for (int combo = 0; combo < 3; ++combo) {
       Tree::M2LList &ML = T.m2l[combo];
-      k_combo_flags<<<cdiv(nf, TB), TB, 0, s>>>(order.p, T.far_ts.p, T.crange.p, nf, combo, flag.p);
+      k_combo_flags<<<cdiv(nf, TB), TB, 0, s>>>(ts_sorted.p, kind.p, nf, combo, flag.p);
       LAUNCH_OK();
       int32_t nk = 0;
       exclusive_scan_i32(flag.p, pos.p, nf, s, &nk);
       ML.n = nk;
-      // output rows in pair order: a cell's rows are contiguous
-      k_flag_by_pair<<<cdiv(nf, TB), TB, 0, s>>>(order.p, flag.p, nf, flag_t.p);
+      // output rows in pair order: a cell's rows are contiguous (the same
+      // flags, taken in pair order)
+      k_combo_flags<<<cdiv(nf, TB), TB, 0, s>>>(T.far_ts.p, kind.p, nf, combo, flag_t.p);
       LAUNCH_OK();
       HIP_OK(hipMemsetAsync(flag_t.p + nf, 0, 4, s));
       exclusive_scan_i32(flag_t.p, pos_t.p, nf + 1, s, nullptr);
@@ -1200,7 +1221,7 @@ void build_tree(Tree &T, const double *verts, int64_t nv, const int32_t *tris, i
       LAUNCH_OK();
       ML.src.alloc(std::max<int32_t>(nk, 1));
       ML.dest.alloc(std::max<int32_t>(nk, 1));
-      k_combo_compact<<<cdiv(nf, TB), TB, 0, s>>>(order.p, key.p, flag.p, pos.p, nf, T.far_ts.p, pos_t.p, ML.src.p,
+      k_combo_compact<<<cdiv(nf, TB), TB, 0, s>>>(order.p, key.p, flag.p, pos.p, nf, ts_sorted.p, pos_t.p, ML.src.p,
                                                   ckeyc.p, ML.dest.p);
       LAUNCH_OK();
       if (nk == 0) continue;

@@ -206,25 +206,22 @@ def test_rebuild_after_destroy_reuses_memory_bitwise():
 
 def test_switches_do_not_change_results(monkeypatch):
     """The near field run concurrently (forked at any point of the upward
-    pass) or after the multipole passes, the FP32 M2L with persistent or
-    one-tile workgroups, and the chip split between the near field and the
-    M2L / downward chain (CU-masked streams), give bitwise the same products
-    (the switches change scheduling, not arithmetic)."""
+    pass) or after the multipole passes, and the FP32 M2L with persistent or
+    one-tile workgroups, give bitwise the same products (the switches change
+    scheduling, not arithmetic)."""
     B = lib()
     p = synth.blobby(5)
     x, y, qv = _inputs(p)
     outs = {}
-    for conc, pers, fork, split in (("1", "1", "-1", "0"), ("0", "1", "-1", "0"), ("1", "0", "-1", "0"),
-                                    ("1", "1", "0", "0"), ("1", "1", "1", "0"), ("1", "1", "2", "0"),
-                                    ("1", "1", "-1", "2"), ("1", "0", "-1", "4")):
+    for conc, pers, fork in (("1", "1", "-1"), ("0", "1", "-1"), ("1", "0", "-1"), ("1", "1", "0"), ("1", "1", "1"),
+                             ("1", "1", "2")):
         monkeypatch.setenv("BEMFMM_CONCURRENT_P2P", conc)
         monkeypatch.setenv("BEMFMM_M2L_PERSISTENT", pers)
         monkeypatch.setenv("BEMFMM_FORK_AT", fork)
-        monkeypatch.setenv("BEMFMM_CU_SPLIT", split)
         t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params())
-        outs[(conc, pers, fork, split)] = {prec: _run_all(B, t, x, y, qv, prec) for prec in (0, 1)}
+        outs[(conc, pers, fork)] = {prec: _run_all(B, t, x, y, qv, prec) for prec in (0, 1)}
         B.tree_destroy(t)
-    ref = outs[("1", "1", "-1", "0")]
+    ref = outs[("1", "1", "-1")]
     for key, o in outs.items():
         for prec in (0, 1):
             for op in range(6):
