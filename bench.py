@@ -22,6 +22,13 @@ on the stream it runs on (inside the timed steps), the BIBEE energy of the
 1.31M-panel blobby surface against the oracle's full dense BIBEE, and the
 oracle's own speed on the host cores (a reported baseline).
 
+The JSON line also carries `extensions`: on the 1.31M-panel blobby surface,
+the FP32 and FP64 A products with and without near quadrature (exact
+close-pair integrals, nu = 2), and the linearised Poisson-Boltzmann
+(screened solvent, kappa = 0.125/A) product, solve to 1e-6 and energy, with
+the screened energy's parity against the dense oracle on the Kirkwood
+sphere (5,120 panels).
+
 Usage: python bench.py [--steps K] [--warmup W] [--config crowded|blobby|kirkwood|differentiation]
 """
 from __future__ import annotations
@@ -98,6 +105,8 @@ def parse():
     ap.add_argument("--no-standalone", action="store_true", help="skip the standalone (near field in line) tree")
     ap.add_argument("--no-bibee-check", action="store_true",
                     help="skip the 1.31M-panel blobby BIBEE against the oracle's full dense BIBEE")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the near-quadrature and linearised Poisson-Boltzmann measurements")
     ap.add_argument("--calib-copy-mb", type=int, default=256,
                     help="size of a plain device copy run before the matvecs, the reference kernel for "
                          "hardware byte counters")
@@ -106,6 +115,83 @@ def parse():
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _event_ms(torch, fn, reps):
+    """Median HIP-event time (ms) of fn() on the current stream over reps calls."""
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return statistics.median(times)
+
+
+def extension_rows(B, torch, synth, params, dev, no_oracle):
+    """Near quadrature and linearised Poisson-Boltzmann on the blobby surface
+    (1.31M panels), with their parity against the oracle on small cases."""
+    import dataclasses
+    pb = synth.config("blobby")
+    N = pb.n_panels
+    x = torch.as_tensor(np.random.default_rng(3).normal(size=N), device=dev)
+    y = torch.empty_like(x)
+    out = {"workload": f"blobby-L8: {N} panels, {pb.n_charges} charges, p=10, theta=0.5, ncrit=64"}
+    # near quadrature: the same tree with and without the close-pair corrections
+    nu = 2.0
+    t0 = B.build_tree(pb.verts, pb.tris, pb.charge_pos, params)
+    tq = B.build_tree(pb.verts, pb.tris, pb.charge_pos, dataclasses.replace(params, near_quad=nu))
+    nq = {"nu": nu, "close_pairs": tq.info["n_nearquad_pairs"]}
+    for prec, name in ((B.FP32, "fp32"), (B.FP64, "fp64")):
+        for t, key in ((t0, "A_ms_one_point"), (tq, "A_ms_near_quad")):
+            for _ in range(3):
+                B.fmm_matvec(t, B.OP_A, prec, x, y)
+            nq[f"{name}_{key}"] = _event_ms(torch, lambda: B.fmm_matvec(t, B.OP_A, prec, x, y), 10)
+    B.tree_destroy(tq)
+    out["near_quad"] = nq
+    # linearised Poisson-Boltzmann, 150 mM (kappa = 0.125 / A)
+    kappa = 0.125
+    q = torch.as_tensor(pb.q, device=dev)
+    uv = torch.as_tensor(np.random.default_rng(4).normal(size=2 * N), device=dev)
+    yy = torch.empty_like(uv)
+    s0 = time.perf_counter()
+    B.lpb_matvec(t0, kappa, uv, yy)  # first call: per-level operators, lists, self integrals
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - s0
+    mv_ms = _event_ms(torch, lambda: B.lpb_matvec(t0, kappa, uv, yy), 5)
+    c0 = time.perf_counter()
+    sol, info = B.lpb_solve(t0, q, kappa, tol=1e-6, maxit=300, restart=50)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - c0
+    dG = B.lpb_energy(t0, q, sol)
+    xs, _ = B.solve_bem(t0, q, tol=1e-6, maxit=300, precision=B.FP64)
+    dG0 = B.solvation_energy(t0, q, xs, precision=B.FP64)
+    B.tree_destroy(t0)
+    lpb = {"kappa_per_A": kappa, "setup_s": setup_s, "matvec_ms": mv_ms, "unknowns": 2 * N,
+           "unknowns_per_s": 2 * N / (mv_ms / 1e3), "solve_s": solve_s, "iters": info.iters,
+           "rel_residual": info.rel_residual, "dG_kcal_mol": dG, "dG_unscreened_kcal_mol": dG0}
+    if not no_oracle:
+        # parity on a case the dense oracle solves: Kirkwood sphere L4, 100 charges
+        import oracle
+        from oracle import lpb as olpb
+        pk = synth.kirkwood(4)
+        g = oracle.geometry(pk.verts, pk.tris)
+        S = olpb.LPB(g, pk.verts, pk.tris, pk.eps_in, pk.eps_out, kappa)
+        o0 = time.perf_counter()
+        want = S.energy(pk.charge_pos, pk.q, S.solve(pk.charge_pos, pk.q))
+        o_s = time.perf_counter() - o0
+        tk = B.build_tree(pk.verts, pk.tris, pk.charge_pos, params)
+        qk = torch.as_tensor(pk.q, device=dev)
+        sk, _ = B.lpb_solve(tk, qk, kappa, tol=1e-10, maxit=400, restart=60)
+        got = B.lpb_energy(tk, qk, sk)
+        B.tree_destroy(tk)
+        lpb["parity_kirkwood_L4"] = {"gpu_kcal_mol": got, "oracle_kcal_mol": want, "rel_err": abs(got - want) / abs(want),
+                                     "oracle_dense_solve_s": o_s}
+    out["lpb"] = lpb
+    return out
 
 
 def main():
@@ -318,6 +404,13 @@ def main():
                        "fp32_rel_err": abs(g32 - want) / abs(want), "fp64_rel_err": abs(g64 - want) / abs(want)}
         log(f"bibee check {bibee_check}")
 
+    # ---- the extensions on the 1.31M-panel blobby surface: near quadrature
+    # (exact close-pair integrals) and the linearised Poisson-Boltzmann solve
+    rows = None
+    if not args.no_rows:
+        rows = extension_rows(B, torch, synth, params, dev, args.no_cpu_baseline)
+        log(f"extension rows {rows}")
+
     out = {
         "metric": METRIC, "value": mv["fp32"]["panels_per_s"], "unit": "panels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -338,6 +431,7 @@ def main():
         "roofline": roofline,
         "roofline_other": roof_m2l if roofline is roof_p2p else roof_p2p,
         "cpu_baseline": cpu,
+        "extensions": rows,
     }
     print(json.dumps(out), flush=True)
 

@@ -364,40 +364,80 @@ __global__ void k_yk_l2p(int p, int ps, int64_t N, const int32_t *__restrict__ p
 // Near field of both kernels together (sorted order): for target t and every
 // panel j != t of its near leaves,
 //   near_u += a_j ((dG0/dn_j - eps dGk/dn_j) u_j - h v_j)
-//   near_v += a_j (d2h/dn_t dn_j u_j - (dG0/dn_t - dGk/dn_t / eps) v_j)
-__global__ void k_lpb_near(int64_t N, const double4 *__restrict__ ca, const double4 *__restrict__ nrm,
-                           const double2 *__restrict__ uvs, const int32_t *__restrict__ pleaf,
-                           const int4 *__restrict__ leaf_range, const int32_t *__restrict__ near_ptr,
-                           const int32_t *__restrict__ near_idx, double kappa, double eps, double2 *__restrict__ out) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= N) return;
-  const double4 ct = ca[t], nt = nrm[t];
-  const int leaf = pleaf[t];
+//   near_v += a_j (d2h/dn_t dn_j u_j - (dG0/dn_t - dGk/dn_t / eps) v_j).
+// One wave per chunk of at most 64 targets of one leaf (the Laplace near
+// field's chunks): a chunk of n targets splits each near leaf's sources over
+// G = 64 / n lane groups, strided; with one group the source index is uniform
+// over the wave and the source records come through the scalar cache.  The G
+// partial sums are added in group order through LDS.  One exponential per
+// pair: h = (1 - exp(-kappa r)) / (4 pi r) and the differences h', h'' are
+// formed from it (their relative rounding grows only as 1/(kappa r)^2, far
+// below the product's truncation error at the distances of a near field).
+__device__ inline void lpb_pair(double tx, double ty, double tz, double ntx, double nty, double ntz, double4 cj,
+                                double4 nj, double2 w, double kappa, double eps, double &su, double &sv) {
   const double q4 = 1.0 / (4.0 * PI);
+  const double dx = tx - cj.x, dy = ty - cj.y, dz = tz - cj.z;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double ir = 1.0 / sqrt(r2), r = r2 * ir;
+  const double kr = kappa * r, ex = exp(-kr);
+  const double ir2 = ir * ir, ir3 = ir2 * ir;
+  const double g0p = -q4 * ir2, g0pp = 2.0 * q4 * ir3;
+  const double gkp = -q4 * ex * (1.0 + kr) * ir2;
+  const double gkpp = q4 * ex * (2.0 + kr * (2.0 + kr)) * ir3;
+  const double h = q4 * (1.0 - ex) * ir;
+  const double hp = g0p - gkp, hpp = g0pp - gkpp;
+  const double nid = (ntx * dx + nty * dy + ntz * dz) * ir;
+  const double njd = (nj.x * dx + nj.y * dy + nj.z * dz) * ir;
+  const double ninj = ntx * nj.x + nty * nj.y + ntz * nj.z;
+  const double d2h = -((hpp - hp * ir) * nid * njd + hp * ir * ninj);
+  su += cj.w * ((eps * gkp - g0p) * njd * w.x - h * w.y);
+  sv += cj.w * (d2h * w.x - (g0p - gkp / eps) * nid * w.y);
+}
+
+__global__ void __launch_bounds__(64) k_lpb_near(const int4 *__restrict__ chunks, const double4 *__restrict__ ca,
+                                                 const double4 *__restrict__ nrm, const double2 *__restrict__ uvs,
+                                                 const int4 *__restrict__ leaf_range,
+                                                 const int32_t *__restrict__ near_ptr,
+                                                 const int32_t *__restrict__ near_idx, double kappa, double eps,
+                                                 double2 *__restrict__ out) {
+  __shared__ double2 red[64];
+  const int4 ch = chunks[blockIdx.x];
+  const int leaf = ch.x, count = ch.z, G = ch.w;
+  const int lane = threadIdx.x;
+  const int g = lane / count, tl = lane - g * count;
+  const bool active = g < G;
+  const int ti = ch.y + (active ? tl : 0);
+  const double4 ct = ca[ti], nt = nrm[ti];
   double su = 0.0, sv = 0.0;
   for (int e = near_ptr[leaf]; e < near_ptr[leaf + 1]; ++e) {
     const int4 rg = leaf_range[near_idx[e]];
-    for (int j = rg.x; j < rg.y; ++j) {
-      if (j == t) continue;
-      const double4 cj = ca[j], nj = nrm[j];
-      const double2 w = uvs[j];
-      const double dx = ct.x - cj.x, dy = ct.y - cj.y, dz = ct.z - cj.z;
-      const double r2 = dx * dx + dy * dy + dz * dz, r = sqrt(r2), ir = 1.0 / r;
-      const double ex = exp(-kappa * r), kr = kappa * r;
-      const double g0p = -q4 * ir * ir, g0pp = 2.0 * q4 * ir * ir * ir;
-      const double gkp = -q4 * ex * (1.0 + kr) * ir * ir;
-      const double gkpp = q4 * ex * (2.0 + 2.0 * kr + kr * kr) * ir * ir * ir;
-      const double h = -q4 * expm1(-kr) * ir;
-      const double hp = g0p - gkp, hpp = g0pp - gkpp;
-      const double nid = (nt.x * dx + nt.y * dy + nt.z * dz) * ir;  // n_t . d / r
-      const double njd = (nj.x * dx + nj.y * dy + nj.z * dz) * ir;  // n_j . d / r
-      const double ninj = nt.x * nj.x + nt.y * nj.y + nt.z * nj.z;
-      const double d2h = -((hpp - hp * ir) * nid * njd + hp * ir * ninj);
-      su += cj.w * ((-g0p * njd + eps * gkp * njd) * w.x - h * w.y);
-      sv += cj.w * (d2h * w.x - (g0p * nid - gkp * nid / eps) * w.y);
+    if (G == 1) {
+      for (int j = rg.x; j < rg.y; ++j) {
+        const double4 cj = ca[j], nj = nrm[j];
+        const double2 w = uvs[j];
+        if (j != ti) lpb_pair(ct.x, ct.y, ct.z, nt.x, nt.y, nt.z, cj, nj, w, kappa, eps, su, sv);
+      }
+    } else if (active) {
+      for (int j = rg.x + g; j < rg.y; j += G) {
+        if (j == ti) continue;
+        lpb_pair(ct.x, ct.y, ct.z, nt.x, nt.y, nt.z, ca[j], nrm[j], uvs[j], kappa, eps, su, sv);
+      }
     }
   }
-  out[t] = make_double2(su, sv);
+  if (G == 1) {
+    if (active) out[ti] = make_double2(su, sv);
+    return;
+  }
+  red[lane] = make_double2(su, sv);
+  __syncthreads();
+  if (g == 0 && active) {
+    for (int k = 1; k < G; ++k) {
+      const double2 o = red[k * count + tl];
+      su += o.x;
+      sv += o.y;
+    }
+    out[ti] = make_double2(su, sv);
+  }
 }
 
 // self integrals over each panel (caller order) of h(R) and -h'(R)/R,
@@ -685,10 +725,12 @@ void lpb_matvec(Tree &T, double kappa, const double *uv, double *y, hipStream_t 
   const bool far = T.L >= 2 && S.list.n > 0;
   if (far) yukawa_far(T, S, kappa, s);
   const int L = T.L;
-  k_lpb_near<<<cdiv(N, 128), 128, 0, s>>>(N, S.ca.p, T.p64nrm.p, S.uvs.p, T.pleaf.p, T.crange.p + T.coff[L],
-                                          T.near_ptr.p + T.near_ptr_off[L], T.near_idx.p + T.near_off[L], kappa, eps,
-                                          S.nr.p);
-  LAUNCH_OK();
+  if (T.nchunk_p > 0) {
+    k_lpb_near<<<(unsigned)T.nchunk_p, 64, 0, s>>>(T.chunk_p.p, S.ca.p, T.p64nrm.p, S.uvs.p, T.crange.p + T.coff[L],
+                                                   T.near_ptr.p + T.near_ptr_off[L], T.near_idx.p + T.near_off[L],
+                                                   kappa, eps, S.nr.p);
+    LAUNCH_OK();
+  }
   k_lpb_combine<<<cdiv(N, TB), TB, 0, s>>>(N, T.pperm.p, uv, S.lap4.p, T.nrm.p, far ? S.yk.p : nullptr, S.nr.p,
                                            S.sv.p, S.sd.p, eps, y);
   LAUNCH_OK();
