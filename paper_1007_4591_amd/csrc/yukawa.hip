@@ -74,7 +74,8 @@ namespace {
 
 constexpr int YQ_T = 32, YQ_P = 64, YQ_N = YQ_T * YQ_P;  // projection rule
 constexpr int YQ_CHUNK = 64;                              // quadrature points per LDS chunk
-constexpr int YK_ACC = 64;                                // projection outputs per thread (p <= 11)
+constexpr int YK_THREADS = 1024;                          // projection workgroup
+constexpr int YK_ACC = 16;                                // projection outputs per thread (p <= 11: 121^2 / 1024 < 15)
 constexpr int SELF_GL = 32;                               // Gauss-Legendre points per edge, self integrals
 
 __constant__ double c_ya[PMAX][PMAX];  // Q_n^m = a z Q_{n-1}^m - b rho^2 Q_{n-2}^m (normalised)
@@ -223,42 +224,65 @@ __device__ inline void yk_khat(int p, double x, double *k) {
   for (int n = 1; n + 1 < p; ++n) k[n + 1] = k[n - 1] + (2 * n + 1) / x * k[n];
 }
 
-// One translation operator per workgroup: T[o][i] = (1 / target radial
-// factor at rho0) * sum over the nodes of w_q Y_o(u_q) B_i(rho0 u_q - C),
-// written in the MFMA B-operand order of the M2L kernel (padding places are
-// left as the caller zeroed them).
-__global__ void __launch_bounds__(256) k_yk_project(int p, int ps, double kappa, const YkTask *__restrict__ tasks,
-                                                    const double4 *__restrict__ quad, double *__restrict__ tables) {
+// One translation operator per workgroup of 1024 threads: T[o][i] =
+// (1 / target radial factor at rho0) * sum over the nodes of
+// w_q Y_o(u_q) B_i(rho0 u_q - C), written in the MFMA B-operand order of the
+// M2L kernel (padding places are left as the caller zeroed them).  Per chunk
+// of 64 nodes, 64 threads evaluate the source basis at their node and 64 the
+// weighted target harmonics (radial factors through LDS); then thread t
+// accumulates column t % p^2 for up to 16 rows.
+__global__ void __launch_bounds__(YK_THREADS) k_yk_project(int p, int ps, double kappa, const YkTask *__restrict__ tasks,
+                                                           const double4 *__restrict__ quad,
+                                                           double *__restrict__ tables) {
   extern __shared__ double smem[];
-  const int np2 = p * p, nout = np2 * np2;
-  double *Bv = smem;                     // [YQ_CHUNK][np2] source basis at the nodes
-  double *Wv = smem + YQ_CHUNK * np2;    // [YQ_CHUNK][np2] w_q Y_o(u_q)
+  const int np2 = p * p;
+  double *Bv = smem;                      // [YQ_CHUNK][np2] source basis at the nodes
+  double *Wv = Bv + YQ_CHUNK * np2;       // [YQ_CHUNK][np2] w_q Y_o(u_q)
+  double *rad = Wv + YQ_CHUNK * np2;      // [YQ_CHUNK][PMAX] radial factors
+  double *aux = rad + YQ_CHUNK * PMAX;    // [YQ_CHUNK][PMAX] work space
+  double *norm = aux + YQ_CHUNK * PMAX;   // [PMAX] 1 / target radial factor at rho0
   const YkTask tk = tasks[blockIdx.x];
   const int tid = threadIdx.x;
+  const int ngroups = YK_THREADS / np2, rows = (np2 + ngroups - 1) / ngroups;
+  const int col = tid % np2, grp = tid / np2;
+  const bool mine = grp < ngroups;
+  if (tid == 0) {
+    if (tk.multipole) {
+      yk_khat(p, kappa * tk.rho0, aux);
+      for (int n = 0; n < p; ++n) norm[n] = 1.0 / (kappa * aux[n]);
+    } else {
+      yk_g(p, kappa, tk.rho0 * tk.rho0, aux, aux + PMAX);
+      double rp = 1.0;
+      for (int n = 0; n < p; ++n) {
+        norm[n] = 1.0 / (aux[n] * rp);
+        rp *= tk.rho0;
+      }
+    }
+  }
+  __syncthreads();
   double acc[YK_ACC];
 #pragma unroll
-  for (int j = 0; j < YK_ACC; ++j) acc[j] = 0.0;
+  for (int k = 0; k < YK_ACC; ++k) acc[k] = 0.0;
   for (int c0 = 0; c0 < YQ_N; c0 += YQ_CHUNK) {
     if (tid < YQ_CHUNK) {
       const double4 u = quad[c0 + tid];
       const double x = tk.rho0 * u.x - tk.cx, y = tk.rho0 * u.y - tk.cy, z = tk.rho0 * u.z - tk.cz;
       const double r2 = x * x + y * y + z * z;
-      double rad[PMAX];
+      double *rd = rad + tid * PMAX, *ax = aux + tid * PMAX;
       if (tk.irregular) {
         const double r = sqrt(r2);
-        double kh[PMAX];
-        yk_khat(p, kappa * r, kh);
+        yk_khat(p, kappa * r, ax);
         double rp = 1.0;  // r^-n
         for (int n = 0; n < p; ++n) {
-          rad[n] = kappa * kh[n] * rp;
+          rd[n] = kappa * ax[n] * rp;
           rp /= r;
         }
       } else {
         double gp[PMAX];
-        yk_g(p, kappa, r2, rad, gp);
+        yk_g(p, kappa, r2, rd, gp);
       }
       double *row = Bv + tid * np2;
-      yk_solid<false>(p, x, y, z, 0.0, 0.0, 0.0, [&](int k, int n, double v, double) { row[k] = rad[n] * v; });
+      yk_solid<false>(p, x, y, z, 0.0, 0.0, 0.0, [&](int k, int n, double v, double) { row[k] = rd[n] * v; });
     } else if (tid < 2 * YQ_CHUNK) {
       const int q = tid - YQ_CHUNK;
       const double4 u = quad[c0 + q];
@@ -266,45 +290,31 @@ __global__ void __launch_bounds__(256) k_yk_project(int p, int ps, double kappa,
       yk_solid<false>(p, u.x, u.y, u.z, 0.0, 0.0, 0.0, [&](int k, int, double v, double) { row[k] = u.w * v; });
     }
     __syncthreads();
+    if (mine) {
+      for (int q = 0; q < YQ_CHUNK; ++q) {
+        const double b = Bv[q * np2 + col];
+        const double *w = Wv + q * np2 + grp * rows;
 #pragma unroll
-    for (int j = 0; j < YK_ACC; ++j) {
-      const int idx = tid + 256 * j;
-      if (idx < nout) {
-        const int o = idx / np2, i = idx - o * np2;
-        double a = acc[j];
-        for (int q = 0; q < YQ_CHUNK; ++q) a += Wv[q * np2 + o] * Bv[q * np2 + i];
-        acc[j] = a;
+        for (int k = 0; k < YK_ACC; ++k)
+          if (k < rows && grp * rows + k < np2) acc[k] += w[k] * b;
       }
     }
     __syncthreads();
   }
-  // target radial factor at rho0
-  double norm[PMAX];
-  if (tk.multipole) {
-    double kh[PMAX];
-    yk_khat(p, kappa * tk.rho0, kh);
-    for (int n = 0; n < p; ++n) norm[n] = 1.0 / (kappa * kh[n]);
-  } else {
-    double g[PMAX], gp[PMAX];
-    yk_g(p, kappa, tk.rho0 * tk.rho0, g, gp);
-    double rp = 1.0;
-    for (int n = 0; n < p; ++n) {
-      norm[n] = 1.0 / (g[n] * rp);
-      rp *= tk.rho0;
-    }
-  }
+  if (!mine) return;
   const int KK = ps / 4, NT = ps / 16;
+  const int pi = coef_pos(col, p, ps);
+  const int gq = pi / KK, kk = pi - gq * KK;
 #pragma unroll
-  for (int j = 0; j < YK_ACC; ++j) {
-    const int idx = tid + 256 * j;
-    if (idx < nout) {
-      const int o = idx / np2, i = idx - o * np2;
+  for (int k = 0; k < YK_ACC; ++k) {
+    const int o = grp * rows + k;
+    if (k < rows && o < np2) {
       int no = 0;
       while ((no + 1) * (no + 1) <= o) ++no;
-      const int po = coef_pos(o, p, ps), pi = coef_pos(i, p, ps);
-      const int ct = po / 16, lo = po - ct * 16, gq = pi / KK, kk = pi - gq * KK;
+      const int po = coef_pos(o, p, ps);
+      const int ct = po / 16, lo = po - ct * 16;
       const size_t at = (((size_t)tk.slot * KK + kk) * NT + ct) * 64 + gq * 16 + lo;
-      tables[at] = acc[j] * norm[no];
+      tables[at] = acc[k] * norm[no];
     }
   }
 }
@@ -374,11 +384,14 @@ __global__ void k_yk_l2p(int p, int ps, int64_t N, const int32_t *__restrict__ p
 // formed from it (their relative rounding grows only as 1/(kappa r)^2, far
 // below the product's truncation error at the distances of a near field).
 __device__ inline void lpb_pair(double tx, double ty, double tz, double ntx, double nty, double ntz, double4 cj,
-                                double4 nj, double2 w, double kappa, double eps, double &su, double &sv) {
+                                double4 nj, double2 w, double kappa, double eps, double ieps, double &su,
+                                double &sv) {
   const double q4 = 1.0 / (4.0 * PI);
   const double dx = tx - cj.x, dy = ty - cj.y, dz = tz - cj.z;
   const double r2 = dx * dx + dy * dy + dz * dz;
-  const double ir = 1.0 / sqrt(r2), r = r2 * ir;
+  // 1/sqrt(r2): the hardware estimate and one Newton step for x^(-1/2)
+  const double y0 = __builtin_amdgcn_rsq(r2);
+  const double ir = __builtin_fma(0.5 * y0, __builtin_fma(-r2 * y0, y0, 1.0), y0), r = r2 * ir;
   const double kr = kappa * r, ex = exp(-kr);
   const double ir2 = ir * ir, ir3 = ir2 * ir;
   const double g0p = -q4 * ir2, g0pp = 2.0 * q4 * ir3;
@@ -391,7 +404,7 @@ __device__ inline void lpb_pair(double tx, double ty, double tz, double ntx, dou
   const double ninj = ntx * nj.x + nty * nj.y + ntz * nj.z;
   const double d2h = -((hpp - hp * ir) * nid * njd + hp * ir * ninj);
   su += cj.w * ((eps * gkp - g0p) * njd * w.x - h * w.y);
-  sv += cj.w * (d2h * w.x - (g0p - gkp / eps) * nid * w.y);
+  sv += cj.w * (d2h * w.x - (g0p - gkp * ieps) * nid * w.y);
 }
 
 __global__ void __launch_bounds__(64) k_lpb_near(const int4 *__restrict__ chunks, const double4 *__restrict__ ca,
@@ -408,6 +421,7 @@ __global__ void __launch_bounds__(64) k_lpb_near(const int4 *__restrict__ chunks
   const bool active = g < G;
   const int ti = ch.y + (active ? tl : 0);
   const double4 ct = ca[ti], nt = nrm[ti];
+  const double ieps = 1.0 / eps;
   double su = 0.0, sv = 0.0;
   for (int e = near_ptr[leaf]; e < near_ptr[leaf + 1]; ++e) {
     const int4 rg = leaf_range[near_idx[e]];
@@ -415,12 +429,12 @@ __global__ void __launch_bounds__(64) k_lpb_near(const int4 *__restrict__ chunks
       for (int j = rg.x; j < rg.y; ++j) {
         const double4 cj = ca[j], nj = nrm[j];
         const double2 w = uvs[j];
-        if (j != ti) lpb_pair(ct.x, ct.y, ct.z, nt.x, nt.y, nt.z, cj, nj, w, kappa, eps, su, sv);
+        if (j != ti) lpb_pair(ct.x, ct.y, ct.z, nt.x, nt.y, nt.z, cj, nj, w, kappa, eps, ieps, su, sv);
       }
     } else if (active) {
       for (int j = rg.x + g; j < rg.y; j += G) {
         if (j == ti) continue;
-        lpb_pair(ct.x, ct.y, ct.z, nt.x, nt.y, nt.z, ca[j], nrm[j], uvs[j], kappa, eps, su, sv);
+        lpb_pair(ct.x, ct.y, ct.z, nt.x, nt.y, nt.z, ca[j], nrm[j], uvs[j], kappa, eps, ieps, su, sv);
       }
     }
   }
@@ -636,6 +650,11 @@ void lpb_setup(Tree &T, double kappa, hipStream_t s) {
         q[i * YQ_P + j] = make_double4(st * std::cos(ph), st * std::sin(ph), x[i], wq[i] * 2.0 * PI / YQ_P);
       }
     }
+    // dynamic LDS beyond 64 KB is allowed once per kernel, here
+    HIP_OK(hipFuncSetAttribute((const void *)k_yk_p2m, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)((size_t)64 * T.p * T.p * sizeof(double))));
+    HIP_OK(hipFuncSetAttribute((const void *)k_yk_project, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(((size_t)2 * YQ_CHUNK * T.p * T.p + 2 * YQ_CHUNK * PMAX + PMAX) * sizeof(double))));
     S.quad.alloc(YQ_N);
     HIP_OK(hipMemcpyAsync(S.quad.p, q.data(), YQ_N * sizeof(double4), hipMemcpyHostToDevice, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -670,9 +689,8 @@ void lpb_setup(Tree &T, double kappa, hipStream_t s) {
   if (!tk.empty()) {
     S.tasks.alloc(tk.size());
     HIP_OK(hipMemcpyAsync(S.tasks.p, tk.data(), tk.size() * sizeof(YkTask), hipMemcpyHostToDevice, s));
-    const size_t shm = (size_t)2 * YQ_CHUNK * T.p * T.p * sizeof(double);
-    HIP_OK(hipFuncSetAttribute((const void *)k_yk_project, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    k_yk_project<<<(unsigned)tk.size(), 256, shm, s>>>(T.p, ps, kappa, S.tasks.p, S.quad.p, S.tables.p);
+    const size_t shm = ((size_t)2 * YQ_CHUNK * T.p * T.p + 2 * YQ_CHUNK * PMAX + PMAX) * sizeof(double);
+    k_yk_project<<<(unsigned)tk.size(), YK_THREADS, shm, s>>>(T.p, ps, kappa, S.tasks.p, S.quad.p, S.tables.p);
     LAUNCH_OK();
   }
   k_lpb_self<<<cdiv(N, 256), 256, 0, s>>>(N, T.pverts.p, T.c.p, kappa, S.sv.p, S.sd.p);
@@ -687,7 +705,6 @@ void yukawa_far(Tree &T, LpbState &S, double kappa, hipStream_t s) {
   const int64_t CL = T.ncell[L];
   double *M = S.M.p, *Lx = S.Lx.p;
   const size_t shm = (size_t)64 * p * p * sizeof(double);
-  HIP_OK(hipFuncSetAttribute((const void *)k_yk_p2m, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
   k_yk_p2m<<<(unsigned)CL, 64, shm, s>>>(p, ps, T.crange.p + T.coff[L], T.p64pos.p, T.p64nrm.p, S.w.p, kappa,
                                          M + (size_t)T.coff[L] * ps);
   LAUNCH_OK();
