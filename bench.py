@@ -43,11 +43,13 @@ import time
 import numpy as np
 
 METRIC = "BEM-FMM matvec panels/s + solve time to 1e-6 rel residual, FP32 vs FP64"
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s of
-# unpacked FP32 vector arithmetic; the published 157.3 needs packed FP32
-# instructions, which this build does not emit.
-PEAK_FP32_VALU = 78.6e12
-PEAK_FP32_PACKED = 157.3e12
+# MI355X published FP32 vector peak, the near field's roofline.  The
+# 4-cycles-per-wave64-instruction model of 256 CUs x 4 SIMDs x 16 lanes x 2
+# (FMA) x 2.4 GHz gives half of it (78.6); the near field's own counters show
+# it retiring VALU instructions faster than that model allows, so the model
+# is reported beside the published peak, not instead of it.
+PEAK_FP32_VALU = 157.3e12
+PEAK_FP32_ISSUE_MODEL = 78.6e12
 PEAK_FP32_MFMA = 157.3e12    # dense FP32 MFMA
 P2P_FLOPS_PER_PAIR = 18      # K' monopole pair: 3 sub, 5 for r^2, 1 rsq, 3 mul, 6 for 3 FMA
 M2L_FLOPS_PER_PAIR = 2 * 100 * 100   # dense p^2 x p^2 contraction at p = 10
@@ -349,7 +351,7 @@ def main():
                 "avg_ms": p2p_ms, "launches": live["p2p"][1],
                 "traffic": pmc_traffic("k_p2p_near<float, 0, 0, 1>", wl)}
     roof_p2p["frac"] = roof_p2p["achieved"] / roof_p2p["peak"]
-    roof_p2p["frac_of_packed_peak"] = roof_p2p["achieved"] / (PEAK_FP32_PACKED / 1e12)
+    roof_p2p["frac_of_issue_model"] = roof_p2p["achieved"] / (PEAK_FP32_ISSUE_MODEL / 1e12)
     roof_m2l = {"bound": "mfma", "kernel": "k_m2l_pers<7,2> (M2L, FP32 MFMA, persistent)",
                 "achieved": m2l_flops / (m2l_ms / 1e3) / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
                 "avg_ms": m2l_ms, "launches": live["m2l"][1], "traffic": pmc_traffic("k_m2l_pers<7, 2>", wl)}
