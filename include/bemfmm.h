@@ -165,7 +165,10 @@ typedef struct {
  * counter-clockwise seen from outside (the normal points into the solvent);
  * charge_pos: [nq*3] (nq may be 0).  The mesh is fixed for the tree's
  * lifetime.  EINVAL: nt == 0, an index out of range, a zero-area or
- * non-finite triangle, a non-finite charge, or parameters out of range.
+ * non-finite triangle, a non-finite charge, or parameters out of range --
+ * among them p outside 1..11: the matrix-core translation kernels hold an
+ * expansion of p^2 coefficients padded to at most eight column tiles of 16
+ * (p^2 <= 128), so p = 12 and above are refused.
  * *out receives a new tree, to be released with bemfmm_tree_destroy. */
 int bemfmm_build_tree(const double *verts, int64_t nv, const int32_t *tris, int64_t nt,
                       const double *charge_pos, int64_t nq, const bemfmm_params *params,
