@@ -371,40 +371,66 @@ __global__ void k_yk_l2p(int p, int ps, int64_t N, const int32_t *__restrict__ p
   out[t] = make_double2(phi, dphi);
 }
 
+// e^{-x} for 0 <= x <= 745 (the near field's kappa r).  With k the integer
+// nearest to 64 x / ln 2, k = 64 n + j (0 <= j < 64) and r = x - k ln 2 / 64
+// (|r| <= ln 2 / 128), e^{-x} = 2^{-n} 2^{-j/64} e^{-r}: 2^{-j/64} comes from
+// a table (tab, 64 entries in LDS) and e^{-r} from its Taylor polynomial of
+// degree 5, whose remainder is below 3.4e-17 relative.  r is reduced with
+// ln 2 / 64 split in two: the leading part has 32 significant bits, so k
+// times it is exact for every k below 2^21 and so is its difference with x;
+// the result is within 2 ulp of e^{-x}.
+__device__ __forceinline__ double exp_neg(double x, const double *tab) {
+  constexpr double C_HI = 0x1.62e42fee00000p-7, C_LO = 0x1.a39ef35793c76p-39;  // ln 2 / 64 = C_HI + C_LO
+  const double k = __builtin_rint(x * (64.0 / 0.69314718055994530942));
+  const double r = __builtin_fma(-k, C_LO, __builtin_fma(-k, C_HI, x));
+  double q = __builtin_fma(r, -1.0 / 120.0, 1.0 / 24.0);
+  q = __builtin_fma(q, r, -1.0 / 6.0);
+  q = __builtin_fma(q, r, 0.5);
+  q = __builtin_fma(q, r, -1.0);
+  q = __builtin_fma(q, r, 1.0);
+  const int ki = (int)k;
+  return __builtin_ldexp(tab[ki & 63] * q, -(ki >> 6));
+}
+
 // Near field of both kernels together (sorted order): for target t and every
 // panel j != t of its near leaves,
 //   near_u += a_j ((dG0/dn_j - eps dGk/dn_j) u_j - h v_j)
 //   near_v += a_j (d2h/dn_t dn_j u_j - (dG0/dn_t - dGk/dn_t / eps) v_j).
-// One wave per chunk of at most 64 targets of one leaf (the Laplace near
-// field's chunks): a chunk of n targets splits each near leaf's sources over
-// G = 64 / n lane groups, strided; with one group the source index is uniform
-// over the wave and the source records come through the scalar cache.  The G
-// partial sums are added in group order through LDS.  One exponential per
-// pair: h = (1 - exp(-kappa r)) / (4 pi r) and the differences h', h'' are
-// formed from it (their relative rounding grows only as 1/(kappa r)^2, far
+// With d = x_t - x_j, r = |d|, E = e^{-kappa r}, A = E (1 + kappa r),
+// B = E (kappa r)^2, p_t = n_t . d, p_j = n_j . d, and every kernel taken
+// without its factor 1/(4 pi) (applied to the sums at the end):
+//   dG0/dn_j - eps dGk/dn_j     = (1 - eps A) p_j / r^3
+//   h                           = (1 - E) / r
+//   d2h/dn_t dn_j               = -((3 - 3A - B) p_t p_j / r^2 + (A - 1) n_t . n_j) / r^3
+//   dG0/dn_t - dGk/dn_t / eps   = (A / eps - 1) p_t / r^3
+// (h' = (A - 1)/r^2 and h'' = (2 - 2A - B)/r^3 are differences of the two
+// kernels' derivatives; their relative rounding grows as 1/(kappa r)^2, far
 // below the product's truncation error at the distances of a near field).
-__device__ inline void lpb_pair(double tx, double ty, double tz, double ntx, double nty, double ntz, double4 cj,
-                                double4 nj, double2 w, double kappa, double eps, double ieps, double &su,
-                                double &sv) {
-  const double q4 = 1.0 / (4.0 * PI);
+// The sources arrive weighted by their areas, (a_j u_j, a_j v_j).  One wave
+// per chunk of at most 64 targets of one leaf (the Laplace near field's
+// chunks): a chunk of n targets splits each near leaf's sources over
+// G = 64 / n lane groups, strided; with one group the source index is
+// uniform over the wave and the source records come through the scalar
+// cache.  The G partial sums are added in group order through LDS.
+__device__ __forceinline__ void lpb_pair(double tx, double ty, double tz, double ntx, double nty, double ntz, double4 cj,
+                                         double4 nj, double2 w, double kappa, double eps, double ieps,
+                                         const double *tab, double &su, double &sv) {
   const double dx = tx - cj.x, dy = ty - cj.y, dz = tz - cj.z;
   const double r2 = dx * dx + dy * dy + dz * dz;
   // 1/sqrt(r2): the hardware estimate and one Newton step for x^(-1/2)
   const double y0 = __builtin_amdgcn_rsq(r2);
-  const double ir = __builtin_fma(0.5 * y0, __builtin_fma(-r2 * y0, y0, 1.0), y0), r = r2 * ir;
-  const double kr = kappa * r, ex = exp(-kr);
-  const double ir2 = ir * ir, ir3 = ir2 * ir;
-  const double g0p = -q4 * ir2, g0pp = 2.0 * q4 * ir3;
-  const double gkp = -q4 * ex * (1.0 + kr) * ir2;
-  const double gkpp = q4 * ex * (2.0 + kr * (2.0 + kr)) * ir3;
-  const double h = q4 * (1.0 - ex) * ir;
-  const double hp = g0p - gkp, hpp = g0pp - gkpp;
-  const double nid = (ntx * dx + nty * dy + ntz * dz) * ir;
-  const double njd = (nj.x * dx + nj.y * dy + nj.z * dz) * ir;
-  const double ninj = ntx * nj.x + nty * nj.y + ntz * nj.z;
-  const double d2h = -((hpp - hp * ir) * nid * njd + hp * ir * ninj);
-  su += cj.w * ((eps * gkp - g0p) * njd * w.x - h * w.y);
-  sv += cj.w * (d2h * w.x - (g0p - gkp * ieps) * nid * w.y);
+  const double ir = __builtin_fma(0.5 * y0, __builtin_fma(-r2 * y0, y0, 1.0), y0);
+  const double kr = kappa * (r2 * ir);
+  const double E = exp_neg(kr, tab);
+  const double A = __builtin_fma(kr, E, E);
+  const double Bk = E * kr * kr;
+  const double ir2 = ir * ir;
+  const double pt = ntx * dx + nty * dy + ntz * dz;
+  const double pj = nj.x * dx + nj.y * dy + nj.z * dz;
+  const double nn = ntx * nj.x + nty * nj.y + ntz * nj.z;
+  su = __builtin_fma(ir, __builtin_fma(__builtin_fma(-eps, A, 1.0) * ir2 * pj, w.x, -(1.0 - E) * w.y), su);
+  const double t1 = __builtin_fma(__builtin_fma(-3.0, A, 3.0) - Bk, pt * pj * ir2, (A - 1.0) * nn);
+  sv = __builtin_fma(-ir * ir2, __builtin_fma(t1, w.x, __builtin_fma(A, ieps, -1.0) * pt * w.y), sv);
 }
 
 __global__ void __launch_bounds__(64) k_lpb_near(const int4 *__restrict__ chunks, const double4 *__restrict__ ca,
@@ -414,9 +440,12 @@ __global__ void __launch_bounds__(64) k_lpb_near(const int4 *__restrict__ chunks
                                                  const int32_t *__restrict__ near_idx, double kappa, double eps,
                                                  double2 *__restrict__ out) {
   __shared__ double2 red[64];
+  __shared__ double tab[64];
   const int4 ch = chunks[blockIdx.x];
   const int leaf = ch.x, count = ch.z, G = ch.w;
   const int lane = threadIdx.x;
+  tab[lane] = exp2(-lane / 64.0);
+  __syncthreads();
   const int g = lane / count, tl = lane - g * count;
   const bool active = g < G;
   const int ti = ch.y + (active ? tl : 0);
@@ -429,17 +458,18 @@ __global__ void __launch_bounds__(64) k_lpb_near(const int4 *__restrict__ chunks
       for (int j = rg.x; j < rg.y; ++j) {
         const double4 cj = ca[j], nj = nrm[j];
         const double2 w = uvs[j];
-        if (j != ti) lpb_pair(ct.x, ct.y, ct.z, nt.x, nt.y, nt.z, cj, nj, w, kappa, eps, ieps, su, sv);
+        if (j != ti) lpb_pair(ct.x, ct.y, ct.z, nt.x, nt.y, nt.z, cj, nj, w, kappa, eps, ieps, tab, su, sv);
       }
     } else if (active) {
       for (int j = rg.x + g; j < rg.y; j += G) {
         if (j == ti) continue;
-        lpb_pair(ct.x, ct.y, ct.z, nt.x, nt.y, nt.z, ca[j], nrm[j], uvs[j], kappa, eps, ieps, su, sv);
+        lpb_pair(ct.x, ct.y, ct.z, nt.x, nt.y, nt.z, ca[j], nrm[j], uvs[j], kappa, eps, ieps, tab, su, sv);
       }
     }
   }
+  const double q4 = 1.0 / (4.0 * PI);
   if (G == 1) {
-    if (active) out[ti] = make_double2(su, sv);
+    if (active) out[ti] = make_double2(q4 * su, q4 * sv);
     return;
   }
   red[lane] = make_double2(su, sv);
@@ -450,7 +480,7 @@ __global__ void __launch_bounds__(64) k_lpb_near(const int4 *__restrict__ chunks
       su += o.x;
       sv += o.y;
     }
-    out[ti] = make_double2(su, sv);
+    out[ti] = make_double2(q4 * su, q4 * sv);
   }
 }
 
@@ -488,7 +518,9 @@ __global__ void k_lpb_self(int64_t N, const double *__restrict__ pv, const doubl
   sd[u] = id;
 }
 
-// sorted copies of the panel data and this product's weights
+// sorted copies of the panel data and this product's weights: the screened
+// expansions' (a v, -eps a u), the near field's area-weighted (a u, a v), and
+// the Laplace dipole weights -a u (caller order)
 __global__ void k_lpb_pack(int64_t N, const int32_t *__restrict__ perm, const double *__restrict__ c,
                            const double *__restrict__ area, const double *__restrict__ uv, double eps,
                            double4 *__restrict__ ca, double2 *__restrict__ w, double2 *__restrict__ uvs,
@@ -499,7 +531,7 @@ __global__ void k_lpb_pack(int64_t N, const int32_t *__restrict__ perm, const do
   const double a = area[u], uu = uv[u], vv = uv[N + u];
   if (ca) ca[t] = make_double4(c[3 * u], c[3 * u + 1], c[3 * u + 2], a);
   w[t] = make_double2(a * vv, -eps * a * uu);
-  uvs[t] = make_double2(uu, vv);
+  uvs[t] = make_double2(a * uu, a * vv);
   wd0[u] = -a * uu;
 }
 
@@ -539,7 +571,7 @@ struct LpbState {
   Tree::M2LList list;               // panel -> panel M2L pairs grouped by (level, offset)
   DBuf<double> M, Lx, m2l_out, rows;
   DBuf<double4> ca;                 // sorted (centroid, area)
-  DBuf<double2> w, uvs, yk, nr;
+  DBuf<double2> w, uvs, yk, nr;    // uvs: sorted (a u, a v)
   DBuf<double> lap4, wd0, sv, sd, b, r;
   DBuf<double4> quad;
   DBuf<YkTask> tasks;
