@@ -28,17 +28,22 @@ def _oracle(p, kappa):
     return OL.LPB(g, p.verts, p.tris, p.eps_in, p.eps_out, kappa)
 
 
-def test_lpb_all_near_tree_matches_oracle():
+@pytest.mark.parametrize("kappa", [0.4, 6.0])
+def test_lpb_all_near_tree_matches_oracle(kappa):
+    """One leaf, so the product is the near field, the self terms and the
+    diagonal alone.  kappa r spans about [0.12, 1.6] at 0.4 and [1.8, 24]
+    at 6 (e^{-kappa r} then runs down to 2^-34, through every entry of the
+    exponential's table); rounding-level agreement either way."""
     B = lib()
     p = synth.born(2)                                   # 320 panels
-    S = _oracle(p, 0.4)
+    S = _oracle(p, kappa)
     t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params(ncrit=4096))
     assert t.info["n_far_pairs"] == 0
     z = np.random.default_rng(3).normal(size=2 * p.n_panels)
-    y = host(B.lpb_matvec(t, 0.4, dev(z)))
+    y = host(B.lpb_matvec(t, kappa, dev(z)))
     want = S.apply(z)
     e = rel_l2(y, want)
-    print(f"[lpb] all-near err={e:.2e}", flush=True)
+    print(f"[lpb] all-near kappa={kappa} err={e:.2e}", flush=True)
     assert e <= 1e-12
     B.tree_destroy(t)
 
