@@ -49,9 +49,9 @@
  *   on `stream` after the multipole passes; BEMFMM_M2L_PERSISTENT=0 uses one
  *   workgroup per M2L tile instead of persistent workgroups (which large
  *   M2Ls use: at least 32 tiles of 256 pairs per compute unit);
- *   BEMFMM_FORK_AT=0, 1 or 2 starts the near field at the start of the
- *   product, after P2M or after M2M (default: after M2M for a large M2L,
- *   else after P2M);
+ *   BEMFMM_FORK_AT=0, 1, 2 or 3 starts the near field at the start of the
+ *   product, after P2M, after M2M or after M2L (default: after M2M for a
+ *   large M2L, else after P2M);
  *   BEMFMM_CACHE_LIMIT_MB caps the device memory kept for reuse per device
  *   (default: half of the device's memory, see bemfmm_release_cache).
  *   Results do not depend on the first three.

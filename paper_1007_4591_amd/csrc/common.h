@@ -33,7 +33,7 @@ constexpr int PMAX = 12;
 // method is run at, Section 4); other orders take the generic kernels
 constexpr int P_FIXED = 10;
 // points of the upward pass where the near field can fork to the second stream
-enum ForkAt { FORK_START = 0, FORK_AFTER_P2M = 1, FORK_AFTER_M2M = 2 };
+enum ForkAt { FORK_START = 0, FORK_AFTER_P2M = 1, FORK_AFTER_M2M = 2, FORK_AFTER_M2L = 3 };
 // M2L work tiles: 4 waves x RT row tiles of 16 pairs
 constexpr int M2L_RT32 = 4, M2L_RT64 = 2;
 constexpr int M2L_ROWS32 = 4 * M2L_RT32 * 16, M2L_ROWS64 = 4 * M2L_RT64 * 16;

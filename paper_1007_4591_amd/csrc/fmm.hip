@@ -1635,6 +1635,7 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
       LAUNCH_OK();
     }
     prof_end(T, ST_M2L, s);
+    if (fork_at == FORK_AFTER_M2L) fork_near();
     // downward pass, levels 2 .. L
     prof_begin(T, ST_L2L, s);
     const Tree::L2LList &LW = T.l2lw;
@@ -1697,7 +1698,7 @@ void fmm_apply(Tree &T, int precision, const FmmRequest &rq, hipStream_t s) {
     T.ev_init = true;
     if (const char *e = getenv("BEMFMM_CONCURRENT_P2P")) T.concurrent = atoi(e) != 0;
     if (const char *e = getenv("BEMFMM_M2L_PERSISTENT")) T.m2l_persistent = atoi(e) != 0;
-    if (const char *e = getenv("BEMFMM_FORK_AT")) T.fork_at = std::min(std::max(atoi(e), -1), (int)FORK_AFTER_M2M);
+    if (const char *e = getenv("BEMFMM_FORK_AT")) T.fork_at = std::min(std::max(atoi(e), -1), (int)FORK_AFTER_M2L);
     int dev = 0;
     HIP_OK(hipGetDevice(&dev));
     HIP_OK(hipDeviceGetAttribute(&T.n_cu, hipDeviceAttributeMultiprocessorCount, dev));

@@ -206,7 +206,7 @@ def test_rebuild_after_destroy_reuses_memory_bitwise():
 
 def test_switches_do_not_change_results(monkeypatch):
     """The near field run concurrently (forked at any point of the upward
-    pass) or after the multipole passes, and the FP32 M2L with persistent or
+    pass, or after M2L) or after the multipole passes, and the FP32 M2L with persistent or
     one-tile workgroups, give bitwise the same products (the switches change
     scheduling, not arithmetic)."""
     B = lib()
@@ -214,7 +214,7 @@ def test_switches_do_not_change_results(monkeypatch):
     x, y, qv = _inputs(p)
     outs = {}
     for conc, pers, fork in (("1", "1", "-1"), ("0", "1", "-1"), ("1", "0", "-1"), ("1", "1", "0"), ("1", "1", "1"),
-                             ("1", "1", "2")):
+                             ("1", "1", "2"), ("1", "1", "3")):
         monkeypatch.setenv("BEMFMM_CONCURRENT_P2P", conc)
         monkeypatch.setenv("BEMFMM_M2L_PERSISTENT", pers)
         monkeypatch.setenv("BEMFMM_FORK_AT", fork)
