@@ -141,6 +141,19 @@ def kprime_exact(verts, tris, normals, i, j):
     return float(np.dot(normals[i], g)) / (4.0 * np.pi)
 
 
+def _correction_values(g, V, pairs):
+    """exact - one-point K' of each close pair (i, j): n_i . grad of the
+    single layer of panel j at c_i, less a_j n_i . grad G(c_i, c_j)."""
+    delta = np.zeros(len(pairs))
+    for k, (i, j) in enumerate(pairs):
+        gi = triangle_grad(V[j], g.c[i][None, :])[0]
+        exact = float(np.dot(g.n[i], gi)) / (4.0 * np.pi)
+        d = g.c[i] - g.c[j]
+        point = -g.a[j] * float(np.dot(g.n[i], d)) / (4.0 * np.pi * np.linalg.norm(d) ** 3)
+        delta[k] = exact - point
+    return delta
+
+
 def kprime_correction(g, verts, tris, nu):
     """Sparse correction of K' for the near-quadrature operator: for every
     close pair (i, j) the difference between K'_ij with the exact integral
@@ -151,15 +164,32 @@ def kprime_correction(g, verts, tris, nu):
     if pairs.size == 0:
         return np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0)
     V = np.asarray(verts, dtype=np.float64)[np.asarray(tris)]
-    rows, cols = pairs[:, 0], pairs[:, 1]
-    delta = np.zeros(len(pairs))
-    for k, (i, j) in enumerate(pairs):
-        gi = triangle_grad(V[j], g.c[i][None, :])[0]
-        exact = float(np.dot(g.n[i], gi)) / (4.0 * np.pi)
-        d = g.c[i] - g.c[j]
-        point = -g.a[j] * float(np.dot(g.n[i], d)) / (4.0 * np.pi * np.linalg.norm(d) ** 3)
-        delta[k] = exact - point
-    return rows, cols, delta
+    return pairs[:, 0], pairs[:, 1], _correction_values(g, V, pairs)
+
+
+def kprime_correction_of(g, verts, tris, nu, panels, side="row"):
+    """The entries of kprime_correction whose row (side="row": target panel)
+    or column (side="col": source panel) is in `panels`, sorted by (row,
+    col), for large meshes: the candidates come from a radius query about
+    those panels' centroids (nu times the largest rho), then the same test
+    |c_i - c_j| < nu rho_j and the same values as kprime_correction."""
+    from scipy.spatial import cKDTree
+
+    V = np.asarray(verts, dtype=np.float64)[np.asarray(tris)]
+    c = V.mean(axis=1)
+    rho = circumradius(verts, tris)
+    kd = cKDTree(c)
+    out = []
+    for p in np.asarray(panels):
+        for q in kd.query_ball_point(c[p], nu * rho.max()):
+            i, j = (p, q) if side == "row" else (q, p)
+            if i != j and np.sum((c[i] - c[j]) ** 2) < (nu * rho[j]) ** 2:
+                out.append((i, j))
+    out = sorted(set(out))
+    pairs = np.array(out, dtype=np.int64).reshape(-1, 2)
+    if pairs.size == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0)
+    return pairs[:, 0], pairs[:, 1], _correction_values(g, V, pairs)
 
 
 def _corr_apply(corr, x, n, transpose=False):

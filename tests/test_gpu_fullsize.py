@@ -7,6 +7,8 @@ import pytest
 
 import oracle
 import synth
+from oracle import lpb as OL
+from oracle import panel_integrals as PI
 
 from gpu_common import requires_gpu, lib, dev, host, rel_l2
 
@@ -207,3 +209,57 @@ def test_linearity():
         y2 = host(B.fmm_matvec(t, 0, prec, dev(x2)))
         y3 = host(B.fmm_matvec(t, 0, prec, dev(2.0 * x1 - 3.0 * x2)))
         assert rel_l2(y3, 2.0 * y1 - 3.0 * y2) <= tol
+
+
+def test_blobby_full_nearquad_sampled_rows():
+    """Near quadrature (nu = 2) on the surface the bench's extension rows
+    time it on (blobby L8, 1.31M panels, about 15M close pairs): sampled
+    rows of A and A^T against the dense oracle's rows plus the
+    exact-minus-one-point corrections of those rows and columns, found by
+    the oracle's own radius search."""
+    B = lib()
+    p = synth.blobby(8)
+    g = oracle.geometry(p.verts, p.tris)
+    nu = 2.0
+    t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params(near_quad=nu))
+    assert t.info["n_nearquad_pairs"] > 10 * p.n_panels
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=p.n_panels)
+    rows = np.sort(rng.choice(p.n_panels, size=128, replace=False))
+    corr = PI.kprime_correction_of(g, p.verts, p.tris, nu, rows, side="row")
+    corrT = PI.kprime_correction_of(g, p.verts, p.tris, nu, rows, side="col")
+    want = oracle.apply_A(g, F, x, rows=rows) - F * PI._corr_apply(corr, x, g.N)[rows]
+    wantT = oracle.apply_AT(g, F, x, rows=rows) - F * PI._corr_apply(corrT, x, g.N, transpose=True)[rows]
+    for prec in (0, 1):
+        e = rel_l2(host(B.fmm_matvec(t, 0, prec, dev(x)))[rows], want)
+        eT = rel_l2(host(B.fmm_matvec(t, 1, prec, dev(x)))[rows], wantT)
+        print(f"[full-nq] blobby-L8 nu={nu} prec={prec} close pairs of the rows {len(corr[0])} / {len(corrT[0])} "
+              f"A err={e:.2e} A^T err={eT:.2e}", flush=True)
+        assert e <= 1e-5 and eT <= 1e-5
+    B.tree_destroy(t)
+
+
+def test_blobby_full_lpb_sampled_rows():
+    """The screened (linearised Poisson-Boltzmann) product on the surface
+    the bench's extension rows time it on (blobby L8, 2,621,440 unknowns,
+    kappa = 0.125/A): sampled rows of both halves against the dense
+    oracle's rows (its self integrals taken for every panel)."""
+    B = lib()
+    p = synth.blobby(8)
+    g = oracle.geometry(p.verts, p.tris)
+    kappa = 0.125
+    S = OL.LPB(g, p.verts, p.tris, p.eps_in, p.eps_out, kappa)
+    t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params())
+    N = p.n_panels
+    z = np.random.default_rng(7).normal(size=2 * N)
+    y = host(B.lpb_matvec(t, kappa, dev(z)))
+    rows = np.sort(np.random.default_rng(8).choice(N, size=48, replace=False))
+    wu, wv = [], []
+    for i in rows:
+        Muu, Muv, Mvu, Mvv = S.rows(i, i + 1)
+        wu.append(Muu[0] @ z[:N] + Muv[0] @ z[N:])
+        wv.append(Mvu[0] @ z[:N] + Mvv[0] @ z[N:])
+    eu, ev = rel_l2(y[rows], np.array(wu)), rel_l2(y[N + rows], np.array(wv))
+    print(f"[full-lpb] blobby-L8 kappa={kappa} err_u={eu:.2e} err_v={ev:.2e}", flush=True)
+    assert eu <= 1e-5 and ev <= 1e-5
+    B.tree_destroy(t)

@@ -196,3 +196,20 @@ def test_near_quadrature_operator_transpose_and_born():
     # the solve is a solve: residual of the near-quadrature operator
     r = PI.apply_A_nq(g, f, xs, corr) - f * oracle.field_B(g, p.charge_pos, p.q)
     assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("side", ["row", "col"])
+def test_near_quadrature_correction_of_given_panels(side):
+    """The restricted search (large meshes: only the pairs of some target or
+    source panels) finds exactly the entries of the full correction list in
+    those rows or columns, with the same values."""
+    p = synth.born(3)
+    g = oracle.geometry(p.verts, p.tris)
+    rows, cols, delta = PI.kprime_correction(g, p.verts, p.tris, 3.0)
+    panels = np.sort(np.random.default_rng(5).choice(g.N, size=60, replace=False))
+    r2, c2, d2 = PI.kprime_correction_of(g, p.verts, p.tris, 3.0, panels, side=side)
+    keep = np.isin(rows if side == "row" else cols, panels)
+    assert keep.sum() > 60
+    np.testing.assert_array_equal(r2, rows[keep])
+    np.testing.assert_array_equal(c2, cols[keep])
+    np.testing.assert_array_equal(d2, delta[keep])
