@@ -90,19 +90,20 @@ def test_crowded_full_sampled_rows():
 
 
 def test_blobby_full_bibee_and_solve():
-    """BIBEE/CFA energy at 1.31M panels vs the dense oracle (B q and C x are
-    N x Q sums); the FP32-refined solve reaches 1e-6 and agrees with the
-    FP64 solve."""
+    """BIBEE energies at 1.31M panels (CFA, P and the +1/2 scale factor) vs
+    the dense oracle (B q and C x are N x Q sums); the FP32-refined solve
+    reaches 1e-6 and agrees with the FP64 solve."""
     B = lib()
     p = synth.blobby(8)
     g = oracle.geometry(p.verts, p.tris)
-    want = oracle.bibee_energy(g, p.charge_pos, p.q, EPS_IN, EPS_OUT, "cfa")
     t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params())
-    got32 = B.bibee_energy(t, dev(p.q), 0, 1)
-    got64 = B.bibee_energy(t, dev(p.q), 0, 0)
-    print(f"[full-bibee] want={want:.8f} fp32={got32:.8f} fp64={got64:.8f}", flush=True)
-    assert abs(got64 - want) <= 1e-5 * abs(want)
-    assert abs(got32 - want) <= 1e-4 * abs(want)
+    for kind, name in ((B.BIBEE_CFA, "cfa"), (B.BIBEE_P, "p"), (B.BIBEE_PLUS_HALF, "plus_half")):
+        want = oracle.bibee_energy(g, p.charge_pos, p.q, EPS_IN, EPS_OUT, name)
+        got32 = B.bibee_energy(t, dev(p.q), kind, 1)
+        got64 = B.bibee_energy(t, dev(p.q), kind, 0)
+        print(f"[full-bibee] {name} want={want:.8f} fp32={got32:.8f} fp64={got64:.8f}", flush=True)
+        assert abs(got64 - want) <= 1e-5 * abs(want)
+        assert abs(got32 - want) <= 1e-4 * abs(want)
     x64, i64 = B.solve_bem(t, dev(p.q), tol=1e-6, precision=0)
     x32, i32 = B.solve_bem(t, dev(p.q), tol=1e-6, precision=2)
     e64 = B.solvation_energy(t, dev(p.q), x64)
