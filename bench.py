@@ -220,8 +220,13 @@ def main():
 
     live = {"p2p": [0.0, 0], "m2l": [0.0, 0]}   # FP32 A products inside the timed steps
 
+    build_ms = []   # build_tree wall time in the timed steps (it returns synchronised)
+
     def step(record=False, count=True):
+        tb = time.perf_counter()
         t = B.build_tree(verts, tris, cpos, params)
+        if count:
+            build_ms.append(1000.0 * (time.perf_counter() - tb))
         if record:
             B.profile(t, True, True)
             B.profile_select(t, B.OP_A, B.FP32)  # other products record nothing
@@ -428,6 +433,9 @@ def main():
         "bibee_vs_dense_oracle": bibee_check,
         "stages_ms_per_matvec_fp32": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
         "tree": tree_sizes,
+        "build_tree": ({"median_ms": statistics.median(build_ms), "min_ms": min(build_ms), "max_ms": max(build_ms),
+                        "steps": len(build_ms), "note": "bemfmm_build_tree wall time inside the timed steps (it "
+                        "returns synchronised); part of ms_per_step"} if build_ms else None),
         "roofline": roofline,
         "roofline_other": roof_m2l if roofline is roof_p2p else roof_p2p,
         "cpu_baseline": cpu,
