@@ -150,6 +150,21 @@ def extension_rows(B, torch, synth, params, dev, no_oracle):
             for _ in range(3):
                 B.fmm_matvec(t, B.OP_A, prec, x, y)
             nq[f"{name}_{key}"] = _event_ms(torch, lambda: B.fmm_matvec(t, B.OP_A, prec, x, y), 10)
+    if not no_oracle:
+        # 64 sampled rows of the near-quadrature A against the dense oracle's
+        # rows plus the corrections of those rows
+        import oracle
+        from oracle import panel_integrals as opi
+        g = oracle.geometry(pb.verts, pb.tris)
+        rows = np.sort(np.random.default_rng(5).choice(N, size=64, replace=False))
+        xh = x.cpu().numpy()
+        f = 1.0 - pb.eps_in / pb.eps_out
+        corr = opi.kprime_correction_of(g, pb.verts, pb.tris, nu, rows, side="row")
+        want = oracle.apply_A(g, f, xh, rows=rows) - f * opi.apply_correction(corr, xh, N)[rows]
+        for prec, name in ((B.FP32, "fp32"), (B.FP64, "fp64")):
+            B.fmm_matvec(tq, B.OP_A, prec, x, y)
+            got = y.cpu().numpy()[rows]
+            nq[f"{name}_rel_err_vs_oracle_64_rows"] = float(np.linalg.norm(got - want) / np.linalg.norm(want))
     B.tree_destroy(tq)
     out["near_quad"] = nq
     # linearised Poisson-Boltzmann, 150 mM (kappa = 0.125 / A)

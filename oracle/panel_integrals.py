@@ -192,7 +192,10 @@ def kprime_correction_of(g, verts, tris, nu, panels, side="row"):
     return pairs[:, 0], pairs[:, 1], _correction_values(g, V, pairs)
 
 
-def _corr_apply(corr, x, n, transpose=False):
+def apply_correction(corr, x, n, transpose=False):
+    """sum over the close pairs (i, j) of delta_ij x_j into row i, or with
+    transpose of delta_ij x_i into row j: the near-quadrature correction of
+    K' x (or K'^T x), without the factor f of A."""
     rows, cols, delta = corr
     out = np.zeros(n)
     if transpose:
@@ -205,13 +208,13 @@ def _corr_apply(corr, x, n, transpose=False):
 def apply_A_nq(g, f, x, corr):
     """A x with the near-quadrature K' (one-point elsewhere)."""
     from .dense import apply_A
-    return apply_A(g, f, x) - f * _corr_apply(corr, np.asarray(x, dtype=np.float64), g.N)
+    return apply_A(g, f, x) - f * apply_correction(corr, np.asarray(x, dtype=np.float64), g.N)
 
 
 def apply_AT_nq(g, f, y, corr):
     """A^T y with the near-quadrature K'."""
     from .dense import apply_AT
-    return apply_AT(g, f, y) - f * _corr_apply(corr, np.asarray(y, dtype=np.float64), g.N, transpose=True)
+    return apply_AT(g, f, y) - f * apply_correction(corr, np.asarray(y, dtype=np.float64), g.N, transpose=True)
 
 
 def solve_nq(g, rq, q, eps_in, eps_out, corr):

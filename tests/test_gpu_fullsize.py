@@ -229,8 +229,8 @@ def test_blobby_full_nearquad_sampled_rows():
     rows = np.sort(rng.choice(p.n_panels, size=128, replace=False))
     corr = PI.kprime_correction_of(g, p.verts, p.tris, nu, rows, side="row")
     corrT = PI.kprime_correction_of(g, p.verts, p.tris, nu, rows, side="col")
-    want = oracle.apply_A(g, F, x, rows=rows) - F * PI._corr_apply(corr, x, g.N)[rows]
-    wantT = oracle.apply_AT(g, F, x, rows=rows) - F * PI._corr_apply(corrT, x, g.N, transpose=True)[rows]
+    want = oracle.apply_A(g, F, x, rows=rows) - F * PI.apply_correction(corr, x, g.N)[rows]
+    wantT = oracle.apply_AT(g, F, x, rows=rows) - F * PI.apply_correction(corrT, x, g.N, transpose=True)[rows]
     for prec in (0, 1):
         e = rel_l2(host(B.fmm_matvec(t, 0, prec, dev(x)))[rows], want)
         eT = rel_l2(host(B.fmm_matvec(t, 1, prec, dev(x)))[rows], wantT)

@@ -37,7 +37,7 @@ def test_nearquad_operators(name, make, nu):
     t1 = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params(ncrit=32, near_quad=nu))
     assert t1.info["n_nearquad_pairs"] == len(corr[0]) and t0.info["n_nearquad_pairs"] == 0
     x = np.random.default_rng(9).normal(size=p.n_panels)
-    dcorr = {B.OP_A: -F * PI._corr_apply(corr, x, g.N), B.OP_AT: -F * PI._corr_apply(corr, x, g.N, transpose=True)}
+    dcorr = {B.OP_A: -F * PI.apply_correction(corr, x, g.N), B.OP_AT: -F * PI.apply_correction(corr, x, g.N, transpose=True)}
     want = {B.OP_A: PI.apply_A_nq(g, F, x, corr), B.OP_AT: PI.apply_AT_nq(g, F, x, corr)}
     for prec in (B.FP64, B.FP32):
         for op in (B.OP_A, B.OP_AT):
