@@ -49,8 +49,12 @@ METRIC = "BEM-FMM matvec panels/s + solve time to 1e-6 rel residual, FP32 vs FP6
 PEAK_FP32_VALU = 157.3e12
 PEAK_FP32_ISSUE_MODEL = 78.6e12
 PEAK_FP32_MFMA = 157.3e12    # dense FP32 MFMA
+PEAK_HBM = 8.0e12            # MI355X HBM3E
 P2P_FLOPS_PER_PAIR = 18      # K' monopole pair: 3 sub, 5 for r^2, 1 rsq, 3 mul, 6 for 3 FMA
 M2L_FLOPS_PER_PAIR = 2 * 100 * 100   # dense p^2 x p^2 contraction at p = 10
+# M2L pair at p = 10: the p^2 FP32 source coefficients in, the p^2 result
+# coefficients out (its row of the pair-ordered output), two int32 indices
+M2L_BYTES_PER_PAIR = 400 + 400 + 8
 # library sources whose code decides the kernels' memory traffic
 TRAFFIC_SOURCES = ("fmm.hip", "tree_build.hip", "common.h")
 
@@ -370,10 +374,18 @@ def main():
                 "traffic": pmc_traffic("k_p2p_near<float, 0, 0, 1>", wl)}
     roof_p2p["frac"] = roof_p2p["achieved"] / roof_p2p["peak"]
     roof_p2p["frac_of_issue_model"] = roof_p2p["achieved"] / (PEAK_FP32_ISSUE_MODEL / 1e12)
-    roof_m2l = {"bound": "mfma", "kernel": "k_m2l_pers<7,2> (M2L, FP32 MFMA, persistent)",
-                "achieved": m2l_flops / (m2l_ms / 1e3) / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                "avg_ms": m2l_ms, "launches": live["m2l"][1], "traffic": pmc_traffic("k_m2l_pers<7, 2>", wl)}
+    # the M2L runs on the bf16 matrix cores (FP32 accuracy from split
+    # operands), which are busy for a small part of its launch: it is bound
+    # by the pair rows it streams, so its roofline is HBM; its useful FP32
+    # flops are reported beside
+    m2l_bytes = info["n_m2l_panel_pairs"] * M2L_BYTES_PER_PAIR
+    roof_m2l = {"bound": "hbm", "kernel": "k_m2l_bf<7,25> (M2L, FP32 by split-bf16 MFMA, persistent)",
+                "achieved": m2l_bytes / (m2l_ms / 1e3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "bytes_per_pair": M2L_BYTES_PER_PAIR, "avg_ms": m2l_ms, "launches": live["m2l"][1],
+                "traffic": pmc_traffic("k_m2l_bf<7, 25>", wl),
+                "useful_tflops": m2l_flops / (m2l_ms / 1e3) / 1e12}
     roof_m2l["frac"] = roof_m2l["achieved"] / roof_m2l["peak"]
+    roof_m2l["useful_frac_of_fp32_mfma"] = roof_m2l["useful_tflops"] / (PEAK_FP32_MFMA / 1e12)
     roofline = roof_p2p if p2p_ms >= m2l_ms else roof_m2l
     tree_sizes = {k: info[k] for k in ("leaf_level", "n_cells", "n_leaves", "n_near_pairs", "n_far_pairs",
                                        "n_m2l_panel_pairs", "n_offsets", "p2p_pairs_panels")}
@@ -394,10 +406,10 @@ def main():
         B.profile(tree_alone, True, True)
         for _ in range(nprof):
             B.fmm_matvec(tree_alone, B.OP_A, B.FP32, xv, yv)
-        for r, stage, flops in ((roof_p2p, "p2p", p2p_flops), (roof_m2l, "m2l", m2l_flops)):
+        for r, stage, work, unit in ((roof_p2p, "p2p", p2p_flops, 1e12), (roof_m2l, "m2l", m2l_bytes, 1e9)):
             ms, n = B.profile_get(tree_alone, f"{stage}/{B.OP_A}/{B.FP32}")
             r["standalone_avg_ms"] = ms / max(n, 1)
-            r["standalone_frac"] = flops / (r["standalone_avg_ms"] / 1e3) / r["peak"] / 1e12
+            r["standalone_frac"] = work / (r["standalone_avg_ms"] / 1e3) / unit / r["peak"]
         B.profile(tree_alone, False, True)
         B.tree_destroy(tree_alone)
         del tree_alone

@@ -47,14 +47,20 @@
  * - Environment switches, read when a tree runs its first product (or, for
  *   the cache, on first use): BEMFMM_CONCURRENT_P2P=0 runs the near field
  *   on `stream` after the multipole passes; BEMFMM_M2L_PERSISTENT=0 uses one
- *   workgroup per M2L tile instead of persistent workgroups (which large
- *   M2Ls use: at least 32 tiles of 256 pairs per compute unit);
+ *   workgroup per M2L tile instead of persistent workgroups (which the FP32
+ *   M2L uses, and the FP64 M2L when it is large: at least 32 tiles of 256
+ *   pairs per compute unit); BEMFMM_M2L_SPLIT=0 runs the persistent FP32 M2L
+ *   of order 10 on FP32 matrix-core products instead of bf16 ones on
+ *   operands split into three bf16 parts;
  *   BEMFMM_FORK_AT=0, 1, 2 or 3 starts the near field at the start of the
  *   product, after P2M, after M2M or after M2L (default: after M2M for a
  *   large M2L, else after P2M);
  *   BEMFMM_CACHE_LIMIT_MB caps the device memory kept for reuse per device
  *   (default: half of the device's memory, see bemfmm_release_cache).
- *   Results do not depend on the first three.
+ *   Results do not depend on BEMFMM_CONCURRENT_P2P or BEMFMM_FORK_AT.  The
+ *   split-bf16 M2L (the default for FP32 at order 10) and the FP32 ones
+ *   selected by the two M2L switches agree to FP32 rounding; the FP32 ones
+ *   agree with each other bitwise.
  */
 #ifndef BEMFMM_H
 #define BEMFMM_H

@@ -229,6 +229,10 @@ struct Tree {
   const Tables *tab = nullptr;
   const float *t_m2l32 = nullptr;   // [noff][PS/4 kk][PS/16 ct][64 lanes], MFMA B-operand order
   const double *t_m2l64 = nullptr;  // same layout
+  // the M2L operators of order P_FIXED as three bf16 parts each (bit
+  // patterns), in the B-operand order of the split-bf16 M2L; null for other
+  // orders
+  const uint16_t *t_m2lbf = nullptr;
   // M2M and L2L: [8 octants][PS/4 kk][PS/16 ct][64 lanes], MFMA B-operand order
   const float *t_m2m32 = nullptr, *t_l2l32 = nullptr;
   const double *t_m2m64 = nullptr, *t_l2l64 = nullptr;
@@ -278,6 +282,7 @@ struct Tree {
   hipStream_t side_stream = nullptr;
   bool concurrent = true;        // near field on the second stream
   bool m2l_persistent = true;    // FP32 M2L: persistent workgroups (else one tile per workgroup)
+  bool m2l_split = true;         // persistent FP32 M2L of order P_FIXED on split-bf16 MFMA (else FP32 MFMA)
   int fork_at = -1;              // where the near field forks: a ForkAt value, -1 = per precision
   int n_cu = 256;                // compute units of the device
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;

@@ -25,6 +25,9 @@ namespace bemfmm {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 template <class R> struct V4;
 template <> struct V4<float> { using T = float4; };
@@ -649,6 +652,273 @@ k_m2l_pers(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ t
   __shared__ float Ts[4 * 16 * (NT * 16 + 4)];
   m2l_tiles<NT, RT>(tile_group, tile_row, group_off, group_end, src, dest, Tsw, M, out, ntiles, Bs, Ts);
 }
+
+// Persistent FP32 M2L on the bf16 matrix cores, for the expansion order with
+// compile-time kernels.  A bf16 step (16x16x32) covers 8x the K of an FP32
+// step (16x16x4) in about half the issue time.  Each FP32 multipole value x
+// is split in registers into three bf16 parts, rounding to nearest at each
+// step, so that x = x1 + x2 + x3 exactly (|x2| <= 2^-8 |x|, |x3| <= 2^-16 |x|);
+// each operator value y is split the same way on the host from its FP64
+// value.  The product keeps the six part products x_i y_j with i + j <= 4,
+// each exact in the FP32 accumulator; what is left out, with the rounding of
+// the operator's split, is below 2^-22 |x y|, the size of FP32 rounding.
+// The rows therefore agree with the FP32 MFMA kernels to rounding, not
+// bitwise, and are themselves deterministic.
+//
+// K layout.  Lane group g = lane / 16 owns block g of the stored row (places
+// g KK .. g KK + RB - 1, the RB real coefficients of the block).  Full steps:
+// for sub-step j < RB / 8 and each of the six part pairs, slot e of lane
+// group g is input place g KK + 8 j + e.  The last R = RB % 8 inputs of
+// every block, for all six pairs, share ceil(6 R / 8) remainder steps: slot
+// 8 s + e holds pair (8 s + e) / R at input 8 (RB / 8) + (8 s + e) % R, and
+// the slots past 6 R are zero.  The host table holds, per offset and column
+// tile, the B operand of every step in that order (parts 1, 2, 3 of each full
+// sub-step, then the remainder steps).
+//
+// Work order is that of k_m2l_pers, with one workgroup of 8 waves per CU:
+// the split operator takes 70 KB of LDS at p = 10 and the store staging
+// 59 KB, so two workgroups do not fit.  A wave takes RT row tiles of 16
+// pairs per unit; the sub-steps run in order, each splitting its 8 inputs
+// just before its products, so that few parts are live at once.  The next
+// unit's rows are requested after the products and before the stores.
+__device__ __forceinline__ void split3(f32x2 x, bf16x2 &h1, bf16x2 &h2, bf16x2 &h3) {
+  h1 = __builtin_convertvector(x, bf16x2);
+  const f32x2 r1 = x - __builtin_convertvector(h1, f32x2);
+  h2 = __builtin_convertvector(r1, bf16x2);
+  const f32x2 r2 = r1 - __builtin_convertvector(h2, f32x2);
+  h3 = __builtin_convertvector(r2, bf16x2);
+}
+
+// Sizes of the split-bf16 M2L for rows of NT column tiles and RB real
+// coefficients per lane-group block.
+template <int NT, int RB>
+struct M2LBf {
+  static constexpr int PS = NT * 16, KK = PS / 4;
+  static constexpr int J = RB / 8, R = RB % 8, NRS = (6 * R + 7) / 8, NBLK = 3 * J + NRS;
+  static constexpr int NW = 8;                 // waves per workgroup
+  static constexpr int TBV = NT * NBLK * 64;   // bf16x8 per operator
+  static constexpr int TS = PS + 4;            // staging row stride (floats, 16-byte aligned)
+};
+
+template <int NT, int RB, int RT>
+__device__ __forceinline__ void m2l_bf_units(const int32_t *__restrict__ tile_group,
+                                             const int32_t *__restrict__ tile_row,
+                                             const int32_t *__restrict__ group_off,
+                                             const int32_t *__restrict__ group_end,
+                                             const int32_t *__restrict__ src, const int32_t *__restrict__ dest,
+                                             const bf16x8 *__restrict__ Tbf, const float *__restrict__ M,
+                                             float *__restrict__ out, int ntiles, bf16x8 *Bs, float *Ts) {
+  using C = M2LBf<NT, RB>;
+  constexpr int PS = C::PS, KK = C::KK, J = C::J, R = C::R, NRS = C::NRS, NBLK = C::NBLK, NW = C::NW;
+  constexpr int TBV = C::TBV, TS = C::TS;
+  constexpr int UROWS = NW * RT * 16;
+  static_assert(M2L_ROWS32 % UROWS == 0, "a tile splits into whole units");
+  constexpr int SUB = M2L_ROWS32 / UROWS;  // units per tile
+  static_assert(RB <= KK && J >= 1, "at least one full sub-step per block");
+  constexpr int F4 = PS / 4;           // float4 per result row
+  constexpr int NV4 = RB / 4;          // float4 loads per block, then RB % 4 scalars
+  // part of x in each of the six products (the host table pairs each with
+  // its part of y)
+  constexpr int PA[6] = {1, 1, 2, 1, 2, 3};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int nwg = gridDim.x;
+  const int wg = xcd_block(blockIdx.x, nwg);
+  const int64_t nunits = (int64_t)ntiles * SUB;
+  const int u0 = (int)(nunits * wg / nwg), u1 = (int)(nunits * (wg + 1) / nwg);
+  if (u0 >= u1) return;  // uniform over the workgroup
+  float *Tw = Ts + wave * 16 * TS;
+
+  struct UnitIn {
+    int g, end, row0;
+  };
+  auto unit_in = [&](int u) {
+    UnitIn v;
+    const int t = u / SUB;
+    v.g = tile_group[t];
+    v.end = group_end[v.g];
+    v.row0 = tile_row[t] + (u - t * SUB) * UROWS + wave * (16 * RT);
+    return v;
+  };
+  // lane (i16, kq) loads the RB real coefficients of block kq of row i16
+  auto load_rows = [&](const UnitIn &v, float (&a)[RT][RB]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int sr = src[min(v.row0 + rt * 16 + i16, v.end - 1)];
+      const float *Mr = M + (size_t)sr * PS + kq * KK;
+      const float4 *M4 = reinterpret_cast<const float4 *>(Mr);
+#pragma unroll
+      for (int q = 0; q < NV4; ++q) {
+        const float4 t = M4[q];
+        a[rt][4 * q] = t.x;
+        a[rt][4 * q + 1] = t.y;
+        a[rt][4 * q + 2] = t.z;
+        a[rt][4 * q + 3] = t.w;
+      }
+#pragma unroll
+      for (int q = 4 * NV4; q < RB; ++q) a[rt][q] = Mr[q];
+    }
+  };
+  auto load_dest = [&](const UnitIn &v, int (&d)[RT]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) d[rt] = dest[min(v.row0 + rt * 16 + i16, v.end - 1)];
+  };
+  auto stage_b = [&](int g) {
+    const bf16x8 *Bg = Tbf + (size_t)group_off[g] * TBV;
+    for (int v = threadIdx.x; v < TBV; v += 64 * NW) Bs[v] = Bg[v];
+  };
+
+  float a[RT][RB];
+  int d[RT];
+  UnitIn cur = unit_in(u0);
+  stage_b(cur.g);
+  load_rows(cur, a);
+  load_dest(cur, d);
+  __syncthreads();
+  for (int u = u0; u < u1; ++u) {
+    const bool work = cur.row0 < cur.end;  // uniform over the wave
+    f32x4 acc[RT][NT];
+    if (work) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+      const bf16x8 *B = Bs + lane;
+      // full sub-steps: the parts of inputs 8j .. 8j+7, split just before use
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        bf16x8 A1[RT], A2[RT], A3[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int e = 0; e < 8; e += 2) {
+            bf16x2 h1, h2, h3;
+            split3(f32x2{a[rt][8 * j + e], a[rt][8 * j + e + 1]}, h1, h2, h3);
+            A1[rt][e] = h1[0], A1[rt][e + 1] = h1[1];
+            A2[rt][e] = h2[0], A2[rt][e + 1] = h2[1];
+            A3[rt][e] = h3[0], A3[rt][e + 1] = h3[1];
+          }
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+          const bf16x8 b1 = B[(ct * NBLK + 3 * j) * 64];
+          const bf16x8 b2 = B[(ct * NBLK + 3 * j + 1) * 64];
+          const bf16x8 b3 = B[(ct * NBLK + 3 * j + 2) * 64];
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) {
+            f32x4 c = acc[rt][ct];
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1[rt], b3, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2[rt], b2, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A3[rt], b1, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1[rt], b2, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2[rt], b1, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1[rt], b1, c, 0, 0, 0);
+            acc[rt][ct] = c;
+          }
+        }
+      }
+      // remainder steps: the last R inputs of the block, all six products
+      if constexpr (NRS > 0) {
+        bf16x8 AR[RT][NRS];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          __bf16 q1[R + 1], q2[R + 1], q3[R + 1];
+#pragma unroll
+          for (int i = 0; i < R; i += 2) {
+            bf16x2 h1, h2, h3;
+            split3(f32x2{a[rt][8 * J + i], i + 1 < R ? a[rt][8 * J + i + 1] : 0.f}, h1, h2, h3);
+            q1[i] = h1[0], q1[i + 1] = h1[1];
+            q2[i] = h2[0], q2[i + 1] = h2[1];
+            q3[i] = h3[0], q3[i + 1] = h3[1];
+          }
+#pragma unroll
+          for (int sr = 0; sr < NRS; ++sr)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int gs = 8 * sr + e;
+              if (gs < 6 * R) {
+                const int idx = gs % R, pa = PA[gs / R];
+                AR[rt][sr][e] = pa == 1 ? q1[idx] : pa == 2 ? q2[idx] : q3[idx];
+              } else {
+                AR[rt][sr][e] = (__bf16)0.f;
+              }
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+          for (int sr = 0; sr < NRS; ++sr) {
+            const bf16x8 br = B[(ct * NBLK + 3 * J + sr) * 64];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AR[rt][sr], br, acc[rt][ct], 0, 0, 0);
+          }
+      }
+    }
+    const bool more = u + 1 < u1;
+    UnitIn nxt = cur;
+    int dn[RT];
+    if (more) {
+      nxt = unit_in(u + 1);
+      load_rows(nxt, a);
+      load_dest(nxt, dn);
+    }
+    __asm__ volatile("" ::: "memory");  // keep the prefetch ahead of the stores
+    if (work) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        // MFMA output: register q of lane (i16, kq) is row 4 kq + q, column
+        // ct * 16 + i16 of column tile ct
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct) Tw[(4 * kq + q) * TS + ct * 16 + i16] = acc[rt][ct][q];
+        __builtin_amdgcn_wave_barrier();
+        // 16 rows x F4 float4, 64 lanes at a time (16 F4 = 64 NT: whole passes)
+#pragma unroll
+        for (int v = 0; v < NT; ++v) {
+          const int f = lane + 64 * v;
+          const int row = f / F4, c4 = f - row * F4;
+          const int dr = __shfl(d[rt], row);
+          const float4 val = *reinterpret_cast<const float4 *>(Tw + row * TS + 4 * c4);
+          if (cur.row0 + rt * 16 + row < cur.end) *reinterpret_cast<float4 *>(out + (size_t)dr * PS + 4 * c4) = val;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    if (more) {
+      if (group_off[nxt.g] != group_off[cur.g]) {
+        __syncthreads();  // every wave is done with the current operator
+        stage_b(nxt.g);
+        __syncthreads();
+      }
+      cur = nxt;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) d[rt] = dn[rt];
+    }
+  }
+}
+
+// The kernel: one row tile per wave, so that a wave needs at most 128
+// registers and four near-field waves per SIMD (56 registers each) can be
+// resident beside the two M2L waves, which leave the matrix cores idle for
+// most of the launch while they wait on memory.  The LDS is dynamic (set at
+// launch) so that the compiler holds the register budget of four waves per
+// SIMD, which a static 128 KB would tell it it cannot reach.
+template <int NT, int RB>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+k_m2l_bf(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ tile_row,
+         const int32_t *__restrict__ group_off, const int32_t *__restrict__ group_end,
+         const int32_t *__restrict__ src, const int32_t *__restrict__ dest, const bf16x8 *__restrict__ Tbf,
+         const float *__restrict__ M, float *__restrict__ out, int ntiles) {
+  using C = M2LBf<NT, RB>;
+  extern __shared__ bf16x8 dyn_lds[];
+  bf16x8 *Bs = dyn_lds;                                   // C::TBV operator entries
+  float *Ts = reinterpret_cast<float *>(dyn_lds + C::TBV);  // store staging
+  m2l_bf_units<NT, RB, 1>(tile_group, tile_row, group_off, group_end, src, dest, Tbf, M, out, ntiles, Bs, Ts);
+}
+constexpr int NT_FIXED = (P_FIXED * P_FIXED + 15) / 16, RB_FIXED = (P_FIXED * P_FIXED + 3) / 4;
+constexpr int M2L_BF_LDS = M2LBf<NT_FIXED, RB_FIXED>::TBV * 16 + M2LBf<NT_FIXED, RB_FIXED>::NW * 16 *
+                                                                   M2LBf<NT_FIXED, RB_FIXED>::TS * 4;
 
 // Persistent FP64 M2L, for large pair counts (on small ones one tile per
 // workgroup is faster).  The FP64 operator (100 KB at p = 10) leaves room in
@@ -1619,7 +1889,13 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
           ML.tile_group.p, ML.tile_row.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p, T.t_m2l32,                 \
           reinterpret_cast<const float *>(M), reinterpret_cast<float *>(m2l));                                 \
     break;
-      switch (NT) {
+      if (!f64 && T.m2l_persistent && T.m2l_split && T.p == P_FIXED && T.t_m2lbf) {
+        k_m2l_bf<NT_FIXED, RB_FIXED>
+            <<<dim3((unsigned)std::min<int64_t>(ML.ntiles * (M2L_ROWS32 / (8 * 16)), T.n_cu)), 512, M2L_BF_LDS, s>>>(
+                ML.tile_group.p, ML.tile_row.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p,
+                reinterpret_cast<const bf16x8 *>(T.t_m2lbf), reinterpret_cast<const float *>(M),
+                reinterpret_cast<float *>(m2l), (int)ML.ntiles);
+      } else switch (NT) {
         M2L_CASE(1)
         M2L_CASE(2)
         M2L_CASE(3)
@@ -1698,6 +1974,10 @@ void fmm_apply(Tree &T, int precision, const FmmRequest &rq, hipStream_t s) {
     T.ev_init = true;
     if (const char *e = getenv("BEMFMM_CONCURRENT_P2P")) T.concurrent = atoi(e) != 0;
     if (const char *e = getenv("BEMFMM_M2L_PERSISTENT")) T.m2l_persistent = atoi(e) != 0;
+    if (const char *e = getenv("BEMFMM_M2L_SPLIT")) T.m2l_split = atoi(e) != 0;
+    // the split-bf16 M2L takes more dynamic LDS than the default limit
+    HIP_OK(hipFuncSetAttribute((const void *)k_m2l_bf<NT_FIXED, RB_FIXED>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               M2L_BF_LDS));
     if (const char *e = getenv("BEMFMM_FORK_AT")) T.fork_at = std::min(std::max(atoi(e), -1), (int)FORK_AFTER_M2L);
     int dev = 0;
     HIP_OK(hipGetDevice(&dev));

@@ -734,7 +734,23 @@ namespace {
 struct DevTables {
   DBuf<float> m2l32, m2m32, l2l32;
   DBuf<double> m2l64, m2m64, l2l64;
+  DBuf<uint16_t> m2lbf;
 };
+
+// bf16 nearest to f (ties to even), as its bit pattern; the tables hold
+// finite values only
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+double bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
 }  // namespace
 
 // Work lists of the batched L2L and M2M products: per level l >= 3, the
@@ -841,6 +857,49 @@ void upload_tables(Tree &T, hipStream_t s) {
     D->m2l64.alloc(sw64.size());
     HIP_OK(hipMemcpyAsync(D->m2l32.p, sw32.data(), sw32.size() * 4, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(D->m2l64.p, sw64.data(), sw64.size() * 8, hipMemcpyHostToDevice, s));
+    // The M2L operators of order P_FIXED for the split-bf16 kernel: each
+    // value y as three bf16 parts, each the nearest to what the previous
+    // ones leave (y1 + y2 + y3 within about 2^-24 |y|).  Per offset and
+    // column tile, NBLK B operands of 64 lanes x 8 slots: for each full
+    // sub-step j, parts 1, 2, 3 of inputs 8j .. 8j+7 of the lane's block;
+    // then the remainder steps, whose slot 8s+e holds, for product
+    // t = (8s+e) / R, part PB[t] of input 8J + (8s+e) % R, and zero past the
+    // six products.  PB pairs with the multipole parts {1,1,2,1,2,3}.
+    std::vector<uint16_t> sbf;
+    if (p == P_FIXED) {
+      const int RB = coef_r4(p), J = RB / 8, R = RB % 8, NRS = (6 * R + 7) / 8, NBLK = 3 * J + NRS;
+      static const int PB[6] = {1, 2, 1, 3, 2, 1};
+      sbf.assign((size_t)noff * NT * NBLK * 64 * 8, 0);
+      for (int o = 0; o < noff; ++o) {
+        const double *Tm = tb.m2l.data() + (size_t)o * ps * ps;
+        for (int ct = 0; ct < NT; ++ct)
+          for (int blk = 0; blk < NBLK; ++blk)
+            for (int l = 0; l < 64; ++l)
+              for (int e = 0; e < 8; ++e) {
+                int part, idx;
+                if (blk < 3 * J) {
+                  part = blk % 3 + 1;
+                  idx = 8 * (blk / 3) + e;
+                } else {
+                  const int gs = 8 * (blk - 3 * J) + e;
+                  if (gs >= 6 * R) continue;
+                  part = PB[gs / R];
+                  idx = 8 * J + gs % R;
+                }
+                const int out = coef_at(ct * 16 + (l % 16), p, ps), in = coef_at((l / 16) * KK + idx, p, ps);
+                if (out < 0 || in < 0) continue;
+                double r = Tm[(size_t)out * ps + in];
+                uint16_t h[3];
+                for (int i = 0; i < 3; ++i) {
+                  h[i] = bf16_bits((float)r);
+                  r -= bf16_value(h[i]);
+                }
+                sbf[((((size_t)o * NT + ct) * NBLK + blk) * 64 + l) * 8 + e] = h[part - 1];
+              }
+      }
+      D->m2lbf.alloc(sbf.size());
+      HIP_OK(hipMemcpyAsync(D->m2lbf.p, sbf.data(), sbf.size() * 2, hipMemcpyHostToDevice, s));
+    }
     // M2M and L2L in the MFMA B-operand order of the M2L tables, one per
     // octant (the batched per-level products reuse the M2L kernel)
     std::vector<double> a((size_t)8 * KK * NT * 64), b(a.size());
@@ -870,6 +929,7 @@ void upload_tables(Tree &T, hipStream_t s) {
   }
   T.t_m2l32 = D->m2l32.p;
   T.t_m2l64 = D->m2l64.p;
+  T.t_m2lbf = D->m2lbf.p;
   T.t_m2m32 = D->m2m32.p;
   T.t_l2l32 = D->l2l32.p;
   T.t_m2m64 = D->m2m64.p;

@@ -206,41 +206,65 @@ def test_rebuild_after_destroy_reuses_memory_bitwise():
 
 def test_switches_do_not_change_results(monkeypatch):
     """The near field run concurrently (forked at any point of the upward
-    pass, or after M2L) or after the multipole passes, and the FP32 M2L with persistent or
-    one-tile workgroups, give bitwise the same products (the switches change
-    scheduling, not arithmetic)."""
+    pass, or after M2L) or after the multipole passes gives bitwise the same
+    products (the switches change scheduling, not arithmetic).  The FP32 M2L
+    on FP32 MFMA gives bitwise the same products with persistent or one-tile
+    workgroups; the split-bf16 M2L (the default at p = 10) differs from it by
+    FP32 rounding only, and FP64 products do not use it."""
     B = lib()
     p = synth.blobby(5)
     x, y, qv = _inputs(p)
     outs = {}
-    for conc, pers, fork in (("1", "1", "-1"), ("0", "1", "-1"), ("1", "0", "-1"), ("1", "1", "0"), ("1", "1", "1"),
-                             ("1", "1", "2"), ("1", "1", "3")):
+    cases = {"base": ("1", "1", "-1", "1"), "in_line": ("0", "1", "-1", "1"),
+             "fork0": ("1", "1", "0", "1"), "fork1": ("1", "1", "1", "1"), "fork2": ("1", "1", "2", "1"),
+             "fork3": ("1", "1", "3", "1"), "fp32_mfma": ("1", "1", "-1", "0"), "per_tile": ("1", "0", "-1", "1")}
+    for name, (conc, pers, fork, split) in cases.items():
         monkeypatch.setenv("BEMFMM_CONCURRENT_P2P", conc)
         monkeypatch.setenv("BEMFMM_M2L_PERSISTENT", pers)
         monkeypatch.setenv("BEMFMM_FORK_AT", fork)
+        monkeypatch.setenv("BEMFMM_M2L_SPLIT", split)
         t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params())
-        outs[(conc, pers, fork)] = {prec: _run_all(B, t, x, y, qv, prec) for prec in (0, 1)}
+        outs[name] = {prec: _run_all(B, t, x, y, qv, prec) for prec in (0, 1)}
         B.tree_destroy(t)
-    ref = outs[("1", "1", "-1")]
-    for key, o in outs.items():
+    ref = outs["base"]
+    for name in ("in_line", "fork0", "fork1", "fork2", "fork3"):
         for prec in (0, 1):
             for op in range(6):
-                assert np.array_equal(o[prec][op], ref[prec][op]), (key, prec, op)
+                assert np.array_equal(outs[name][prec][op], ref[prec][op]), (name, prec, op)
+    for prec in (0, 1):
+        for op in range(6):
+            assert np.array_equal(outs["per_tile"][prec][op], outs["fp32_mfma"][prec][op]), (prec, op)
+            if prec == 0:
+                assert np.array_equal(outs["fp32_mfma"][prec][op], ref[prec][op]), op
+            else:
+                d = rel_l2(ref[prec][op], outs["fp32_mfma"][prec][op])
+                print(f"  op {op}: split-bf16 vs FP32 MFMA M2L, rel L2 {d:.2e}", flush=True)
+                assert d <= 1e-6, (op, d)
 
 
 def test_persistent_m2l_matches_per_tile_at_full_size(monkeypatch):
     """At the bench surface (1.31M panels) the M2L is large enough to run
     persistent in both precisions (and the near field forks after M2M); the
-    one-tile-per-workgroup kernels give bitwise the same products."""
+    one-tile-per-workgroup kernels give bitwise the same products as the
+    persistent ones on FP32 MFMA, and the split-bf16 M2L agrees with them to
+    FP32 rounding."""
     B = lib()
     p = synth.blobby(8)
     x = np.random.default_rng(9).normal(size=p.n_panels)
     outs = {}
-    for pers in ("1", "0"):
+    for pers, split in (("1", "0"), ("0", "0"), ("1", "1")):
         monkeypatch.setenv("BEMFMM_M2L_PERSISTENT", pers)
+        monkeypatch.setenv("BEMFMM_M2L_SPLIT", split)
         t = B.build_tree(p.verts, p.tris, p.charge_pos, B.Params())
         assert t.info["n_m2l_panel_pairs"] > 32 * 256 * 256
-        outs[pers] = [host(B.fmm_matvec(t, op, prec, dev(x))) for op in (0, 1) for prec in (0, 1)]
+        outs[pers + split] = [host(B.fmm_matvec(t, op, prec, dev(x))) for op in (0, 1) for prec in (0, 1)]
         B.tree_destroy(t)
-    for a, b in zip(outs["1"], outs["0"]):
+    for a, b in zip(outs["10"], outs["00"]):
         assert np.array_equal(a, b)
+    for k, (a, b) in enumerate(zip(outs["11"], outs["10"])):
+        if k % 2 == 0:  # FP64
+            assert np.array_equal(a, b)
+        else:
+            d = rel_l2(a, b)
+            print(f"  split-bf16 vs FP32 MFMA M2L, op {k // 2}: rel L2 {d:.2e}", flush=True)
+            assert d <= 1e-6
