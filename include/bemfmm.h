@@ -53,8 +53,9 @@
  *   of order 10 on FP32 matrix-core products instead of bf16 ones on
  *   operands split into three bf16 parts;
  *   BEMFMM_FORK_AT=0, 1, 2 or 3 starts the near field at the start of the
- *   product, after P2M, after M2M or after M2L (default: after M2M for a
- *   large M2L, else after P2M);
+ *   product, after P2M, after M2M or after M2L (default: after M2M when the
+ *   M2L has at least 32 tiles of 256 pairs per compute unit, or 8 for the
+ *   split-bf16 FP32 M2L, else after P2M);
  *   BEMFMM_CACHE_LIMIT_MB caps the device memory kept for reuse per device
  *   (default: half of the device's memory, see bemfmm_release_cache).
  *   Results do not depend on BEMFMM_CONCURRENT_P2P or BEMFMM_FORK_AT.  The

@@ -677,7 +677,9 @@ k_m2l_pers(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ t
 //
 // Work order is that of k_m2l_pers, with one workgroup of 8 waves per CU:
 // the split operator takes 70 KB of LDS at p = 10 and the store staging
-// 59 KB, so two workgroups do not fit.  A wave takes RT row tiles of 16
+// 52 KB, so two workgroups do not fit.  A result row holds the coefficients
+// in packed order (100 reals at p = 10), without the padding places of the
+// stored layout; the downward pass reads it so.  A wave takes RT row tiles of 16
 // pairs per unit; the sub-steps run in order, each splitting its 8 inputs
 // just before its products, so that few parts are live at once.  The next
 // unit's rows are requested after the products and before the stores.
@@ -697,7 +699,8 @@ struct M2LBf {
   static constexpr int J = RB / 8, R = RB % 8, NRS = (6 * R + 7) / 8, NBLK = 3 * J + NRS;
   static constexpr int NW = 8;                 // waves per workgroup
   static constexpr int TBV = NT * NBLK * 64;   // bf16x8 per operator
-  static constexpr int TS = PS + 4;            // staging row stride (floats, 16-byte aligned)
+  static constexpr int CS = 4 * RB;            // reals per result row (compact: no padding places)
+  static constexpr int TS = CS + 4;            // staging row stride (floats, 16-byte aligned)
 };
 
 template <int NT, int RB, int RT>
@@ -710,12 +713,13 @@ __device__ __forceinline__ void m2l_bf_units(const int32_t *__restrict__ tile_gr
                                              float *__restrict__ out, int ntiles, bf16x8 *Bs, float *Ts) {
   using C = M2LBf<NT, RB>;
   constexpr int PS = C::PS, KK = C::KK, J = C::J, R = C::R, NRS = C::NRS, NBLK = C::NBLK, NW = C::NW;
-  constexpr int TBV = C::TBV, TS = C::TS;
+  constexpr int TBV = C::TBV, TS = C::TS, CS = C::CS;
+  static_assert(CS % 4 == 0, "compact rows of whole float4");
   constexpr int UROWS = NW * RT * 16;
   static_assert(M2L_ROWS32 % UROWS == 0, "a tile splits into whole units");
   constexpr int SUB = M2L_ROWS32 / UROWS;  // units per tile
   static_assert(RB <= KK && J >= 1, "at least one full sub-step per block");
-  constexpr int F4 = PS / 4;           // float4 per result row
+  constexpr int F4 = CS / 4;           // float4 per result row
   constexpr int NV4 = RB / 4;          // float4 loads per block, then RB % 4 scalars
   // part of x in each of the six products (the host table pairs each with
   // its part of y)
@@ -867,20 +871,33 @@ __device__ __forceinline__ void m2l_bf_units(const int32_t *__restrict__ tile_gr
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         // MFMA output: register q of lane (i16, kq) is row 4 kq + q, column
-        // ct * 16 + i16 of column tile ct
+        // ct * 16 + i16 of column tile ct, the coefficient stored at that
+        // place; it goes to its compact place (block * RB + offset), and the
+        // padding places are left out
+        // (the lane index is passed through an empty asm so that the
+        // compiler computes the places here instead of holding all of them
+        // in registers for the whole loop)
+        int il = i16;
+        __asm__ volatile("" : "+v"(il));
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int ct = 0; ct < NT; ++ct) {
+          const int pl = ct * 16 + il, blk = pl / KK, o = pl - blk * KK;
+          if (o < RB) {
 #pragma unroll
-          for (int ct = 0; ct < NT; ++ct) Tw[(4 * kq + q) * TS + ct * 16 + i16] = acc[rt][ct][q];
+            for (int q = 0; q < 4; ++q) Tw[(4 * kq + q) * TS + blk * RB + o] = acc[rt][ct][q];
+          }
+        }
         __builtin_amdgcn_wave_barrier();
-        // 16 rows x F4 float4, 64 lanes at a time (16 F4 = 64 NT: whole passes)
+        // 16 rows x F4 float4, 64 lanes at a time
+        constexpr int NPASS = (16 * F4 + 63) / 64;
 #pragma unroll
-        for (int v = 0; v < NT; ++v) {
-          const int f = lane + 64 * v;
+        for (int v = 0; v < NPASS; ++v) {
+          const int f = min(lane + 64 * v, 16 * F4 - 1);
           const int row = f / F4, c4 = f - row * F4;
           const int dr = __shfl(d[rt], row);
           const float4 val = *reinterpret_cast<const float4 *>(Tw + row * TS + 4 * c4);
-          if (cur.row0 + rt * 16 + row < cur.end) *reinterpret_cast<float4 *>(out + (size_t)dr * PS + 4 * c4) = val;
+          if (lane + 64 * v < 16 * F4 && cur.row0 + rt * 16 + row < cur.end)
+            *reinterpret_cast<float4 *>(out + (size_t)dr * CS + 4 * c4) = val;
         }
         __builtin_amdgcn_wave_barrier();
       }
@@ -919,6 +936,7 @@ k_m2l_bf(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ til
 constexpr int NT_FIXED = (P_FIXED * P_FIXED + 15) / 16, RB_FIXED = (P_FIXED * P_FIXED + 3) / 4;
 constexpr int M2L_BF_LDS = M2LBf<NT_FIXED, RB_FIXED>::TBV * 16 + M2LBf<NT_FIXED, RB_FIXED>::NW * 16 *
                                                                    M2LBf<NT_FIXED, RB_FIXED>::TS * 4;
+static_assert(M2LBf<NT_FIXED, RB_FIXED>::CS == P_FIXED * P_FIXED, "compact rows hold the p^2 coefficients");
 
 // Persistent FP64 M2L, for large pair counts (on small ones one tile per
 // workgroup is faster).  The FP64 operator (100 KB at p = 10) leaves room in
@@ -1029,17 +1047,20 @@ template <> struct VecT<double> { using T = double2; static constexpr int W = 2;
 
 // One wave per cell of level l: L = L2L(parent) + sum of the cell's M2L
 // results.  The cell's result rows are one contiguous run (kptr), read with
-// vector loads: a row takes ps/W lanes, so several rows are read per step
-// by lane groups, U rows in flight per group; every lane keeps a compensated
-// sum, and the groups are added in group order; the L2L term (a batched
-// MFMA product per level, l2l[cell of the level][ps]) is added last.  At the
-// leaf level the kernel also writes the evaluation coefficients
-// E[leaf][4][ps] of the potential and of its gradient (see L2P).
+// vector loads: a row of rs reals takes rs/W lanes, so several rows are
+// read per step by lane groups, U rows in flight per group; every lane keeps
+// a compensated sum, and the groups are added in group order; the L2L term
+// (a batched MFMA product per level, l2l[cell of the level][ps]) is added
+// last.  Rows are either in the stored layout (rs = ps) or compact (the
+// split-bf16 M2L: rs = p^2 coefficients in packed order, no padding places),
+// whose sums go to their places.  At the leaf level the kernel also writes
+// the evaluation coefficients E[leaf][4][ps] of the potential and of its
+// gradient (see L2P).
 template <class R>
-__global__ void __launch_bounds__(256) k_downward(int p, int ps, int64_t c0, int64_t C, int with_parent,
-                                                  const R *__restrict__ l2l, const int32_t *__restrict__ kptr,
-                                                  const R *__restrict__ m2l, R *__restrict__ Lx, int leaf, R inv_s,
-                                                  R *__restrict__ E) {
+__global__ void __launch_bounds__(256) k_downward(int p, int ps, int rs, int compact, int64_t c0, int64_t C,
+                                                  int with_parent, const R *__restrict__ l2l,
+                                                  const int32_t *__restrict__ kptr, const R *__restrict__ m2l,
+                                                  R *__restrict__ Lx, int leaf, R inv_s, R *__restrict__ E) {
   using VT = typename VecT<R>::T;
   constexpr int W = VecT<R>::W;
   constexpr int U = 8;
@@ -1051,7 +1072,7 @@ __global__ void __launch_bounds__(256) k_downward(int p, int ps, int64_t c0, int
   if (blockIdx.x >= C) return;
   const int lane = threadIdx.x;
   const int np2 = p * p;
-  const int lpr = ps / W;                     // lanes per row
+  const int lpr = rs / W;                     // lanes per row
   const int groups = nthr / lpr;              // rows per step
   const int grp = lane / lpr, k4 = lane - grp * lpr;
   const bool act = grp < groups;
@@ -1089,9 +1110,11 @@ __global__ void __launch_bounds__(256) k_downward(int p, int ps, int64_t c0, int
   }
 #pragma unroll
   for (int w = 0; w < W; ++w) part[lane * W + w] = s[w];
+  if (compact)
+    for (int k = lane; k < ps; k += nthr) Ls[k] = R(0);  // the padding places
   __syncthreads();
-  // group totals in group order -> Ls[k]
-  for (int k = lane; k < ps; k += nthr) {
+  // group totals in group order -> Ls[place of k]
+  for (int k = lane; k < rs; k += nthr) {
     const int kk = k / W, w = k - kk * W;
     R acc = part[kk * W + w], cc = R(0);
     for (int h = 1; h < groups; ++h) {
@@ -1100,7 +1123,7 @@ __global__ void __launch_bounds__(256) k_downward(int p, int ps, int64_t c0, int
       cc = (t - acc) - y;
       acc = t;
     }
-    Ls[k] = acc;
+    Ls[compact ? coef_pos(k, p, ps) : k] = acc;
   }
   __syncthreads();
   if (with_parent) {
@@ -1797,17 +1820,22 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   // The near field runs on the second stream, forked from the caller's
   // stream at a point of the upward pass and joined before L2P.  It forks
   // after P2M, except for an M2L large enough to keep persistent workgroups
-  // busy for a while (at least 32 tiles of 256 pairs per CU): that M2L runs
-  // persistent (in FP64 too) and the fork comes after M2M, so that the M2L
-  // workgroups (most of a SIMD's registers) are resident before near-field
-  // waves fill the chip, and the near field takes the rest.  Smaller M2L
-  // runs one tile per workgroup in FP64.
+  // busy for a while (at least 32 tiles of 256 pairs per CU; 8 for the
+  // split-bf16 M2L, whose waves leave room for near-field waves): that M2L
+  // runs persistent (in FP64 too) and the fork comes after M2M, so that the
+  // M2L workgroups are resident before near-field waves fill the chip, and
+  // the near field takes the rest.  Smaller M2L runs one tile per workgroup
+  // in FP64.
   const hipStream_t ss = T.concurrent ? T.side_stream : s;
   const int combo = src_charges ? 1 : (rq.tgt == TGT_CHARGE ? 2 : 0);
   const Tree::M2LList &ML = T.m2l[combo];
   const bool far = (L >= 2) && T.nfar > 0;
   const bool big_m2l = T.m2l_persistent && ML.ntiles >= 32 * (int64_t)T.n_cu;
-  const int fork_at = !far ? FORK_START : T.fork_at >= 0 ? T.fork_at : (big_m2l ? FORK_AFTER_M2M : FORK_AFTER_P2M);
+  // the split-bf16 M2L leaves registers for near-field waves beside it, so
+  // it gains from going first from 8 tiles per CU on (the others from 32)
+  const bool split_m2l = !f64 && T.m2l_persistent && T.m2l_split && T.p == P_FIXED && T.t_m2lbf;
+  const bool m2l_first = split_m2l ? ML.ntiles >= 8 * (int64_t)T.n_cu : big_m2l;
+  const int fork_at = !far ? FORK_START : T.fork_at >= 0 ? T.fork_at : (m2l_first ? FORK_AFTER_M2M : FORK_AFTER_P2M);
   auto fork_near = [&]() {
     if (rq.far_only) return;
     HIP_OK(hipEventRecord(T.ev_fork, s));
@@ -1889,7 +1917,7 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
           ML.tile_group.p, ML.tile_row.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p, T.t_m2l32,                 \
           reinterpret_cast<const float *>(M), reinterpret_cast<float *>(m2l));                                 \
     break;
-      if (!f64 && T.m2l_persistent && T.m2l_split && T.p == P_FIXED && T.t_m2lbf) {
+      if (split_m2l) {
         k_m2l_bf<NT_FIXED, RB_FIXED>
             <<<dim3((unsigned)std::min<int64_t>(ML.ntiles * (M2L_ROWS32 / (8 * 16)), T.n_cu)), 512, M2L_BF_LDS, s>>>(
                 ML.tile_group.p, ML.tile_row.p, ML.group_off.p, ML.group_end.p, ML.src.p, ML.dest.p,
@@ -1926,7 +1954,8 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
       // the load latency) take four waves per cell
       const int nthr = T.ncell[l] < 4 * T.n_cu * 8 ? 256 : 64;
       const size_t shm2 = (size_t)(ps + nthr * VecT<R>::W) * sizeof(R);
-      k_downward<R><<<T.ncell[l], nthr, shm2, s>>>(p, ps, T.coff[l], T.ncell[l], l > 2 ? 1 : 0, l2l, ML.kptr.p,
+      k_downward<R><<<T.ncell[l], nthr, shm2, s>>>(p, ps, split_m2l ? p * p : ps, split_m2l ? 1 : 0, T.coff[l],
+                                                   T.ncell[l], l > 2 ? 1 : 0, l2l, ML.kptr.p,
                                                    m2l, Lx, leaf ? 1 : 0, R(1.0 / sL), E);
       LAUNCH_OK();
     }
@@ -2036,7 +2065,7 @@ void downward64(Tree &T, int l, const double *l2l_rows, const int32_t *kptr, con
   const int ps = T.ps;
   const int nthr = T.ncell[l] < 4 * T.n_cu * 8 ? 256 : 64;
   const size_t shm = (size_t)(ps + nthr * VecT<double>::W) * sizeof(double);
-  k_downward<double><<<T.ncell[l], nthr, shm, s>>>(T.p, ps, T.coff[l], T.ncell[l], l > 2 ? 1 : 0, l2l_rows, kptr,
+  k_downward<double><<<T.ncell[l], nthr, shm, s>>>(T.p, ps, ps, 0, T.coff[l], T.ncell[l], l > 2 ? 1 : 0, l2l_rows, kptr,
                                                    m2l_rows, Lx, 0, 1.0, nullptr);
   LAUNCH_OK();
 }
