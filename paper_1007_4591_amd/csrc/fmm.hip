@@ -1073,7 +1073,10 @@ __global__ void __launch_bounds__(256) k_downward(int p, int ps, int rs, int com
   const int lane = threadIdx.x;
   const int np2 = p * p;
   const int lpr = rs / W;                     // lanes per row
-  const int groups = nthr / lpr;              // rows per step
+  // rows per step, from the stored row length whatever the row format, so
+  // that every coefficient is summed over the same rows in the same order
+  // from compact and from stored rows
+  const int groups = nthr / (ps / W);
   const int grp = lane / lpr, k4 = lane - grp * lpr;
   const bool act = grp < groups;
   R s[W], comp[W];
@@ -1835,6 +1838,8 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   // it gains from going first from 8 tiles per CU on (the others from 32)
   const bool split_m2l = !f64 && T.m2l_persistent && T.m2l_split && T.p == P_FIXED && T.t_m2lbf;
   const bool m2l_first = split_m2l ? ML.ntiles >= 8 * (int64_t)T.n_cu : big_m2l;
+  // M2L result rows without the padding places (read so by the downward pass)
+  const bool compact_rows = split_m2l;
   const int fork_at = !far ? FORK_START : T.fork_at >= 0 ? T.fork_at : (m2l_first ? FORK_AFTER_M2M : FORK_AFTER_P2M);
   auto fork_near = [&]() {
     if (rq.far_only) return;
@@ -1954,7 +1959,7 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
       // the load latency) take four waves per cell
       const int nthr = T.ncell[l] < 4 * T.n_cu * 8 ? 256 : 64;
       const size_t shm2 = (size_t)(ps + nthr * VecT<R>::W) * sizeof(R);
-      k_downward<R><<<T.ncell[l], nthr, shm2, s>>>(p, ps, split_m2l ? p * p : ps, split_m2l ? 1 : 0, T.coff[l],
+      k_downward<R><<<T.ncell[l], nthr, shm2, s>>>(p, ps, compact_rows ? p * p : ps, compact_rows ? 1 : 0, T.coff[l],
                                                    T.ncell[l], l > 2 ? 1 : 0, l2l, ML.kptr.p,
                                                    m2l, Lx, leaf ? 1 : 0, R(1.0 / sL), E);
       LAUNCH_OK();
