@@ -113,19 +113,19 @@ __host__ __device__ inline int idx_im(int n, int m) { return n * n + 2 * m; }
 // Storage order of every expansion row (multipole, local, and the rows of
 // the M2L, M2M and L2L products).  A row of ps = pad16(p^2) reals is four
 // blocks of ps/4; coefficient k (the packed index above) goes to place
-// k mod r4 of block k div r4, with r4 = ceil(p^2/4), and the rest of each
-// block is zero.  The MFMA products take one block per lane group along K,
-// so the k-steps from r4 on would multiply zeros only and are skipped.
+// k div 4 of block k mod 4, so every block holds at most r4 = ceil(p^2/4)
+// coefficients and the rest of it is zero.  The MFMA products take one block
+// per lane group along K, so the k-steps from r4 on would multiply zeros
+// only and are skipped; and a k-step takes consecutive coefficients (4 for
+// FP32 and FP64 MFMA, 32 for bf16), of neighbouring degrees and so of
+// similar size, which keeps the sums inside one instruction close to exact.
 __host__ __device__ inline int coef_r4(int p) { return (p * p + 3) / 4; }
-__host__ __device__ inline int coef_pos(int k, int p, int ps) {
-  const int r4 = coef_r4(p);
-  return (k / r4) * (ps / 4) + k % r4;
-}
+__host__ __device__ inline int coef_pos(int k, int p, int ps) { return (k & 3) * (ps / 4) + (k >> 2); }
 // inverse of coef_pos: the coefficient stored at place i, or -1 (padding)
 __host__ __device__ inline int coef_at(int i, int p, int ps) {
-  const int r4 = coef_r4(p), b = i / (ps / 4), o = i - b * (ps / 4);
-  const int k = b * r4 + o;
-  return (o < r4 && k < p * p) ? k : -1;
+  const int b = i / (ps / 4), o = i - b * (ps / 4);
+  const int k = 4 * o + b;
+  return k < p * p ? k : -1;
 }
 // k-steps of an MFMA product over rows of NT column tiles: the largest r4 of
 // the orders whose rows have NT tiles (pad16(p^2) = 16 NT)

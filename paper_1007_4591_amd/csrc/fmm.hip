@@ -666,7 +666,10 @@ k_m2l_pers(const int32_t *__restrict__ tile_group, const int32_t *__restrict__ t
 // bitwise, and are themselves deterministic.
 //
 // K layout.  Lane group g = lane / 16 owns block g of the stored row (places
-// g KK .. g KK + RB - 1, the RB real coefficients of the block).  Full steps:
+// g KK .. g KK + RB - 1, its RB coefficients; in the interleaved storage
+// order a full sub-step j covers the packed coefficients 32 j .. 32 j + 31,
+// of neighbouring degrees, so the products one instruction sums are of
+// similar size and its truncating sum loses little).  Full steps:
 // for sub-step j < RB / 8 and each of the six part pairs, slot e of lane
 // group g is input place g KK + 8 j + e.  The last R = RB % 8 inputs of
 // every block, for all six pairs, share ceil(6 R / 8) remainder steps: slot
@@ -872,8 +875,8 @@ __device__ __forceinline__ void m2l_bf_units(const int32_t *__restrict__ tile_gr
       for (int rt = 0; rt < RT; ++rt) {
         // MFMA output: register q of lane (i16, kq) is row 4 kq + q, column
         // ct * 16 + i16 of column tile ct, the coefficient stored at that
-        // place; it goes to its compact place (block * RB + offset), and the
-        // padding places are left out
+        // place; it goes to its compact place, its packed index
+        // (4 * offset + block), and the padding places are left out
         // (the lane index is passed through an empty asm so that the
         // compiler computes the places here instead of holding all of them
         // in registers for the whole loop)
@@ -884,7 +887,7 @@ __device__ __forceinline__ void m2l_bf_units(const int32_t *__restrict__ tile_gr
           const int pl = ct * 16 + il, blk = pl / KK, o = pl - blk * KK;
           if (o < RB) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Tw[(4 * kq + q) * TS + blk * RB + o] = acc[rt][ct][q];
+            for (int q = 0; q < 4; ++q) Tw[(4 * kq + q) * TS + 4 * o + blk] = acc[rt][ct][q];
           }
         }
         __builtin_amdgcn_wave_barrier();
