@@ -8,7 +8,9 @@
 // while the P2P near field runs on a second stream and is joined before L2P.
 //
 // Every stage is templated on the working precision (float or double); the
-// FP32 path uses v_mfma_f32_16x16x4f32 and v_rsq_f32, the FP64 path
+// FP32 path uses v_mfma_f32_16x16x4f32 (M2M, L2L, M2L at other orders),
+// v_mfma_f32_16x16x32_bf16 on operands split into three bf16 parts (M2L at
+// the compile-time order) and v_rsq_f32, the FP64 path
 // v_mfma_f64_16x16x4f64 and a refined FP64 reciprocal square root.
 // Accumulation orders are fixed (no floating-point atomics), so results are
 // reproducible run to run.
