@@ -50,8 +50,9 @@
  *   workgroup per M2L tile instead of persistent workgroups (which the FP32
  *   M2L uses, and the FP64 M2L when it is large: at least 32 tiles of 256
  *   pairs per compute unit); BEMFMM_M2L_SPLIT=0 runs the persistent FP32 M2L
- *   of order 10 on FP32 matrix-core products instead of bf16 ones on
- *   operands split into three bf16 parts;
+ *   of order 10 of the panel-to-panel products (A, A^T) on FP32 matrix-core
+ *   products instead of bf16 ones on operands split into three bf16 parts
+ *   (products from or to charges always use the FP32 ones);
  *   BEMFMM_FORK_AT=0, 1, 2 or 3 starts the near field at the start of the
  *   product, after P2M, after M2M or after M2L (default: after M2M when the
  *   M2L has at least 32 tiles of 256 pairs per compute unit, or 8 for the
@@ -59,9 +60,9 @@
  *   BEMFMM_CACHE_LIMIT_MB caps the device memory kept for reuse per device
  *   (default: half of the device's memory, see bemfmm_release_cache).
  *   Results do not depend on BEMFMM_CONCURRENT_P2P or BEMFMM_FORK_AT.  The
- *   split-bf16 M2L (the default for FP32 at order 10) and the FP32 ones
- *   selected by the two M2L switches agree to FP32 rounding; the FP32 ones
- *   agree with each other bitwise.
+ *   split-bf16 M2L (the default for FP32 A and A^T at order 10) and the FP32
+ *   ones selected by the two M2L switches agree to FP32 rounding; the FP32
+ *   ones agree with each other bitwise.
  */
 #ifndef BEMFMM_H
 #define BEMFMM_H

@@ -1839,9 +1839,14 @@ static void run_fmm(Tree &T, PrecBufs &B, const FmmRequest &rq, hipStream_t s) {
   const Tree::M2LList &ML = T.m2l[combo];
   const bool far = (L >= 2) && T.nfar > 0;
   const bool big_m2l = T.m2l_persistent && ML.ntiles >= 32 * (int64_t)T.n_cu;
-  // the split-bf16 M2L leaves registers for near-field waves beside it, so
-  // it gains from going first from 8 tiles per CU on (the others from 32)
-  const bool split_m2l = !f64 && T.m2l_persistent && T.m2l_split && T.p == P_FIXED && T.t_m2lbf;
+  // The split-bf16 M2L runs the panel-to-panel products (A, A^T), where it
+  // agrees with the FP32 MFMA kernel to about 1e-9.  Products from or to
+  // charges keep the FP32 MFMA kernel: their FP32 sums are more sensitive
+  // (an energy sums them over the charges), and they are a small part of a
+  // solve.  It leaves registers for near-field waves beside it, so it gains
+  // from going first from 8 tiles per CU on (the others from 32).
+  const bool split_m2l =
+      !f64 && combo == 0 && T.m2l_persistent && T.m2l_split && T.p == P_FIXED && T.t_m2lbf;
   const bool m2l_first = split_m2l ? ML.ntiles >= 8 * (int64_t)T.n_cu : big_m2l;
   // M2L result rows without the padding places (read so by the downward pass)
   const bool compact_rows = split_m2l;
